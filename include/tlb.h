@@ -1,0 +1,130 @@
+/*
+ * tlb.h -- C interface of the MI355X (gfx950) library that steps the vielbein lattice
+ * Boltzmann binary-fluid model on a periodic torus (Ambrus, Busuioc, Wagner, Paillusson,
+ * Kusumaatmaja, arXiv:1904.10070).
+ *
+ * State.  Sixteen velocity-space populations f_k(theta_q, phi_s) of the Q = 4 Hermite set
+ * (section II C, eq. vmatrix) plus the Cahn-Hilliard order parameter phi(theta_q, phi_s)
+ * (section II B, eq. CH) on the node grid theta_q = 2 pi q / n_theta, phi_s = 2 pi s / n_phi,
+ * periodic in both angles (section II C, after eq. boltz_tor).  Population index
+ * k = 4 i + j: i picks v^theta-hat = v_i, j picks v^phi-hat = v_j, with
+ * v = (-sqrt(3+sqrt6), -sqrt(3-sqrt6), +sqrt(3-sqrt6), +sqrt(3+sqrt6)).
+ *
+ * Layout.  Every field lives in device memory as a dense structure of arrays of the
+ * precision's element type T (float for precision 32, double for 64):
+ *     f   : T[16][n_theta][n_phi]       (phi index fastest)
+ *     phi, n, u_theta, u_phi, mu : T[n_theta][n_phi]
+ * u_theta, u_phi are the orthonormal (vielbein) components of the fluid velocity.
+ *
+ * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
+ * buffers); they must outlive the grid handle.  The library owns only its per-row geometry
+ * table and a small reduction workspace, both freed by tlb_destroy.
+ *
+ * Streams.  All work is enqueued on the HIP stream given at creation (NULL = the default
+ * stream), in call order, asynchronously with respect to the host.  Only tlb_invariants
+ * waits for the stream.  A handle must not be used from two host threads at once.
+ *
+ * Errors.  Every int32_t-returning function returns TLB_OK (0) or a negative TLB_E* code;
+ * tlb_last_error() then returns a message for the calling thread.
+ */
+#ifndef TLB_H
+#define TLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TLB_OK 0
+#define TLB_EINVAL (-1)     /* bad argument: parameters out of range, NULL where required   */
+#define TLB_ENOMEM (-2)     /* the library's own small allocation failed                    */
+#define TLB_EHIP (-3)       /* a HIP runtime call or kernel launch failed                    */
+#define TLB_ENONFINITE (-4) /* tlb_invariants found NaN or Inf in the state                  */
+
+/* flags */
+#define TLB_FLAT 1u            /* flat limit: J = R and G = 0 (a doubly periodic plane with   *
+                                * spacings R dphi and r dtheta)                              */
+#define TLB_CH_NO_ADVECTION 2u /* drop -div(u phi) from the Cahn-Hilliard equation          */
+
+/* Physical and numerical parameters, in the paper's units (k_B T = m = 1, so the kinematic
+ * viscosity is nu = tau, eq. nu).
+ *   r, R        minor and major radius, 0 < r < R (a = r/R < 1 keeps R + r cos theta > 0)
+ *   n_theta     nodes round the tube, n_phi nodes round the symmetry axis (each >= 1)
+ *   A, kappa    Landau free-energy parameters (eq. Landau), kappa >= 0
+ *   M           Cahn-Hilliard mobility (eq. CH), >= 0
+ *   tau         BGK relaxation time (> 0)
+ *   dt          time step of the three-stage SSP Runge-Kutta integrator (> 0)
+ *   precision   32 or 64: element type T of every device buffer of this grid
+ *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION                                              */
+typedef struct tlb_params {
+  double r, R;
+  int32_t n_theta, n_phi;
+  double A, kappa, M, tau, dt;
+  int32_t precision;
+  uint32_t flags;
+} tlb_params;
+
+/* The three state copies the integrator cycles through (device pointers, each of the
+ * layout above).  Copy 0 holds the current state between calls; copies 1 and 2 hold
+ * Runge-Kutta stage values and are scratch to the caller.  All six must be distinct.   */
+typedef struct tlb_buffers {
+  void* f[3];
+  void* phi[3];
+} tlb_buffers;
+
+typedef struct tlb_grid tlb_grid;
+
+/* Validate the parameters, build the per-row geometry of the torus (appendix A: metric
+ * factors r and J = R + r cos theta at the nodes and half-nodes, connection coefficient
+ * G = Gamma_{theta phi phi} = sin theta / J, eq. conn_torus) and the velocity-space
+ * constants (eq. vmatrix, the weights w_k and the derivative kernel K^H of section II C),
+ * and return a handle.  Errors: TLB_EINVAL (r <= 0, R <= r, a grid side < 1, dt, tau <= 0,
+ * kappa or M < 0, precision not 32/64, any NULL pointer or buffer), TLB_ENOMEM, TLB_EHIP. */
+int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffers,
+                              void* hip_stream, tlb_grid** out);
+
+/* Load a state.  phi (required) is copied into state copy 0.  If f is non-NULL it is copied
+ * as the populations; otherwise the populations are set to the discrete equilibrium
+ * f_eq(n, u) of eq. feq from the moment fields n, u_theta, u_phi (then all three required).
+ * Device pointers of element type T; stream-ordered.  Errors: TLB_EINVAL, TLB_EHIP.        */
+int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void* n,
+                      const void* u_theta, const void* u_phi);
+
+/* Advance n_steps >= 0 time steps.  One step is three right-hand-side evaluations of the
+ * semi-discrete system -- moments; chemical potential mu = A phi (phi^2 - 1) - kappa
+ * Delta_S phi (eq. mu); interface force n F = -phi grad mu (eq. pbin); BGK relaxation to
+ * f_eq (eq. feq); finite-difference advection along the vielbein frame with the metric
+ * factors r and J (eq. boltz_tor); velocity-space force and connection terms through K^H
+ * (section II C); Cahn-Hilliard right-hand side -div(u phi) + M Delta_S mu (eq. CH) --
+ * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous.
+ * Errors: TLB_EINVAL, TLB_EHIP (launch failure).                                           */
+int32_t tlb_step_n(tlb_grid* grid, int64_t n_steps);
+
+/* Moments of the current state into caller buffers (any may be NULL): density n = sum f,
+ * velocity u = sum f v / n (section II C), the order parameter phi, and the chemical
+ * potential mu (eq. mu).  Device pointers of element type T; stream-ordered.               */
+int32_t tlb_get_moments(tlb_grid* grid, void* n, void* u_theta, void* u_phi, void* phi,
+                        void* mu);
+
+/* Copy the current state (checkpoint) into caller buffers (either may be NULL).
+ * tlb_set_state(grid, f, phi, ...) with the same buffers restores it exactly.              */
+int32_t tlb_get_state(tlb_grid* grid, void* f, void* phi);
+
+/* Conservation diagnostics of the current state, reduced in FP64 in a fixed order (hence
+ * bit-reproducible): out[0] = total mass sum_q,s r J_q dtheta dphi n, out[1] = the same
+ * area-weighted sum of phi, out[2] = number of non-finite values in (f, phi).  out is a
+ * host array of 3 doubles.  Waits for the stream.  Returns TLB_ENONFINITE if out[2] > 0.  */
+int32_t tlb_invariants(tlb_grid* grid, double out[3]);
+
+/* Release the handle and the library's own device memory (not the caller's buffers).      */
+void tlb_destroy(tlb_grid* grid);
+
+/* Message of the last error on the calling thread ("" if none).  Owned by the library.   */
+const char* tlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLB_H */

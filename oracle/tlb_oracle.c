@@ -1,0 +1,559 @@
+/*
+ * tlb_oracle.c -- plain CPU reference ("oracle") for the vielbein lattice Boltzmann
+ * binary-fluid step on a periodic torus, after Ambrus, Busuioc, Wagner, Paillusson and
+ * Kusumaatmaja, "Multicomponent Flow on Curved Surfaces: A Vielbein Lattice Boltzmann
+ * Approach" (arXiv:1904.10070).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent checker of the HIP library under
+ * paper_1904_10070_amd/.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no source, header, table or helper with the GPU path.
+ *
+ * Everything is written the slow, obvious way: separate passes over the grid, one term per
+ * array, plain loops, no blocking or fusion.  The arithmetic type is `real`: double by
+ * default; the same source built with -DTLBREF_REAL=float runs every operation in single
+ * precision and gives an independent FP32 error envelope.  Build with -ffp-contract=off so
+ * that no multiply-add is fused behind the reader's back.
+ *
+ * Notation (section II and appendix A of the paper):
+ *   theta in [0,2pi) goes round the tube (minor radius r), phi in [0,2pi) round the symmetry
+ *   axis (major radius R); node (q,s) sits at theta_q = q dtheta, phi_s = s dphi.
+ *   J(theta) = R + r cos(theta) = omega^phi-hat_phi; the area element is r J dtheta dphi.
+ *   Populations f_k with k = 4 i + j: i indexes v^theta-hat = v_i, j indexes v^phi-hat = v_j.
+ *   Storage: f[k][q][s] (s fastest), phi[q][s].
+ *
+ * Readings where the paper defers to its supplementary material (not available):
+ *   - spatial derivative in the Boltzmann advection: conservative finite-difference flux form,
+ *     face values by the fifth-order upwind (UW5) linear reconstruction, upwind by sign(v);
+ *   - Cahn-Hilliard: second-order central flux form with face averages;
+ *   - time stepping: three-stage strong-stability-preserving Runge-Kutta (Shu-Osher form) on
+ *     the joint state (f, phi);
+ *   - interface force in the potential form n F = -phi grad mu, central differences;
+ *   - the velocity in f_eq and in the CH advection is u = sum f v / n (no force shift).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef TLBREF_REAL
+#define TLBREF_REAL double
+#endif
+typedef TLBREF_REAL real;
+#define RC(x) ((real)(x)) /* a constant in the arithmetic type */
+
+#define TLBREF_FLAT 1u            /* J = R, G = 0: the flat periodic Cartesian limit        */
+#define TLBREF_CH_NO_ADVECTION 2u /* drop the u phi flux from Cahn-Hilliard                */
+
+#define TLBREF_OK 0
+#define TLBREF_EINVAL (-1)
+#define TLBREF_ENOMEM (-2)
+#define TLBREF_ENONFINITE (-4)
+
+typedef struct {
+  double r, R;
+  int32_t n_theta, n_phi;
+  double A, kappa, M, tau, dt;
+  uint32_t flags;
+} tlbref_params;
+
+typedef struct {
+  tlbref_params p;
+  int nt, np;
+  size_t nn; /* nodes per plane */
+  /* parameters in the arithmetic type */
+  real r, dth, dph, A, kappa, M, tau, dt;
+  /* velocity set and derivative matrices (section II C) */
+  real v[4], w[4], K[4][4], Kt[4][4];
+  /* per-row geometry (appendix A) */
+  real *J, *Jp, *Jm, *G;
+  /* state and scratch */
+  real *f, *phi;   /* y^n             */
+  real *f1, *phi1; /* RK stage values */
+  real *f2, *phi2;
+  real *Lf, *Lphi; /* right-hand side */
+  /* per-node intermediates of one right-hand-side evaluation */
+  real *n, *ut, *up, *lap, *mu, *Fth, *Fph;
+  real *adv, *frc, *con, *bgk; /* the four Boltzmann terms, [16][nt][np] each */
+  int64_t steps;
+} tlbref_grid;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Hermite polynomials He_n, orthogonal with weight exp(-v^2/2)/sqrt(2 pi) (section II C).     */
+static double hermite(int n, double x) {
+  double hm1 = 1.0, h = x;
+  if (n == 0) return 1.0;
+  for (int k = 1; k < n; ++k) {
+    double hp1 = x * h - k * hm1; /* He_{k+1} = x He_k - k He_{k-1} */
+    hm1 = h;
+    h = hp1;
+  }
+  return h;
+}
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int k = 2; k <= n; ++k) f *= k;
+  return f;
+}
+
+/* Q = 4 velocity set: roots of He_4 (eq. vmatrix), weights w_k = Q!/He_{Q+1}(v_k)^2, and the
+ * velocity-derivative kernels K^H and K~^H as sums over Hermite polynomials (section II C). */
+static void velocity_set(double v[4], double w[4], double K[4][4], double Kt[4][4]) {
+  const int Q = 4;
+  const double a = sqrt(3.0 + sqrt(6.0)), b = sqrt(3.0 - sqrt(6.0));
+  v[0] = -a; v[1] = -b; v[2] = b; v[3] = a;
+  for (int k = 0; k < Q; ++k) {
+    double h = hermite(Q + 1, v[k]);
+    w[k] = factorial(Q) / (h * h);
+  }
+  for (int i = 0; i < Q; ++i)
+    for (int m = 0; m < Q; ++m) {
+      double s = 0.0, st = 0.0;
+      for (int l = 0; l < Q; ++l) {
+        double c = hermite(l + 1, v[i]) / factorial(l);
+        s += c * hermite(l, v[m]);
+        st += c * (hermite(l + 1, v[m]) + (l > 0 ? l * hermite(l - 1, v[m]) : 0.0));
+      }
+      K[i][m] = -w[i] * s;
+      Kt[i][m] = -w[i] * st;
+    }
+}
+
+static int wrap(int x, int n) {
+  int m = x % n;
+  return m < 0 ? m + n : m;
+}
+
+#define IDX(g, q, s) ((size_t)(q) * (size_t)(g)->np + (size_t)(s))
+#define FIDX(g, k, q, s) ((size_t)(k) * (g)->nn + IDX(g, q, s))
+
+/* ------------------------------------------------------------------------------------------ */
+/* Equilibrium distribution (eq. feq): third-order Hermite expansion of the Maxwellian.       */
+static real feq_one(const tlbref_grid* g, int i, int j, real n, real ut, real up) {
+  real vu = g->v[i] * ut + g->v[j] * up;
+  real u2 = ut * ut + up * up;
+  return n * g->w[i] * g->w[j] *
+         (RC(1) + vu + RC(0.5) * (vu * vu - u2) + (RC(1) / RC(6)) * vu * (vu * vu - RC(3) * u2));
+}
+
+/* Fifth-order upwind reconstruction of h at the face between h0 and hp1, for a positive
+ * transport velocity; the stencil is h_{-2}..h_{+2}. */
+static real uw5_face(real hm2, real hm1, real h0, real hp1, real hp2) {
+  return (RC(2) * hm2 - RC(13) * hm1 + RC(47) * h0 + RC(27) * hp1 - RC(3) * hp2) / RC(60);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One evaluation of the right-hand side L(f, phi) of the semi-discrete system.                */
+static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* Lphi) {
+  const int nt = g->nt, np = g->np;
+  const real r = g->r, dth = g->dth, dph = g->dph;
+  const real A = g->A, kappa = g->kappa, M = g->M, tau = g->tau;
+  const int ch_adv = !(g->p.flags & TLBREF_CH_NO_ADVECTION);
+
+  /* 1. moments n = sum f, n u = sum f v (section II C) */
+#pragma omp parallel for schedule(static)
+  for (int q = 0; q < nt; ++q)
+    for (int s = 0; s < np; ++s) {
+      real n = RC(0), nut = RC(0), nup = RC(0);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          real fk = f[FIDX(g, 4 * i + j, q, s)];
+          n += fk;
+          nut += fk * g->v[i];
+          nup += fk * g->v[j];
+        }
+      g->n[IDX(g, q, s)] = n;
+      g->ut[IDX(g, q, s)] = nut / n;
+      g->up[IDX(g, q, s)] = nup / n;
+    }
+
+  /* 2. surface Laplace-Beltrami of phi in flux form,
+   *      Delta_S phi = 1/(r^2 J) d_theta (J d_theta phi) + 1/J^2 d_phi^2 phi,
+   *    with J at the half-nodes theta_q +/- dtheta/2 on the theta faces.
+   * 3. chemical potential mu = -A phi (1 - phi^2) - kappa Delta_S phi  (eq. mu)             */
+#pragma omp parallel for schedule(static)
+  for (int q = 0; q < nt; ++q) {
+    int qp = wrap(q + 1, nt), qm = wrap(q - 1, nt);
+    for (int s = 0; s < np; ++s) {
+      int sp = wrap(s + 1, np), sm = wrap(s - 1, np);
+      real ph = phi[IDX(g, q, s)];
+      real flux_up = g->Jp[q] * (phi[IDX(g, qp, s)] - ph) / dth;
+      real flux_dn = g->Jm[q] * (ph - phi[IDX(g, qm, s)]) / dth;
+      real lap_th = (flux_up - flux_dn) / (r * r * g->J[q] * dth);
+      real lap_ph = (phi[IDX(g, q, sp)] - RC(2) * ph + phi[IDX(g, q, sm)]) /
+                    (g->J[q] * g->J[q] * dph * dph);
+      real lap = lap_th + lap_ph;
+      g->lap[IDX(g, q, s)] = lap;
+      g->mu[IDX(g, q, s)] = -A * ph * (RC(1) - ph * ph) - kappa * lap;
+    }
+  }
+
+  /* 4. interface force n F = -phi grad mu (eq. pbin, potential form) in vielbein components,
+   *    grad^theta-hat = (1/r) d_theta and grad^phi-hat = (1/J) d_phi, central differences.
+   * 8. Cahn-Hilliard right-hand side (eq. CH): -div(u phi) + M Delta_S mu, with
+   *    div V = 1/(r J) d_theta (J V^theta-hat) + 1/J d_phi V^phi-hat in flux form, face values
+   *    of the flux averaged from the two neighbouring nodes.                                 */
+#pragma omp parallel for schedule(static)
+  for (int q = 0; q < nt; ++q) {
+    int qp = wrap(q + 1, nt), qm = wrap(q - 1, nt);
+    for (int s = 0; s < np; ++s) {
+      int sp = wrap(s + 1, np), sm = wrap(s - 1, np);
+      size_t c = IDX(g, q, s);
+      real ph = phi[c], n = g->n[c];
+      real dmu_th = (g->mu[IDX(g, qp, s)] - g->mu[IDX(g, qm, s)]) / (RC(2) * r * dth);
+      real dmu_ph = (g->mu[IDX(g, q, sp)] - g->mu[IDX(g, q, sm)]) / (RC(2) * g->J[q] * dph);
+      g->Fth[c] = -ph * dmu_th / n;
+      g->Fph[c] = -ph * dmu_ph / n;
+
+      /* M Delta_S mu with the same five-point operator as in step 2 */
+      real mu0 = g->mu[c];
+      real fu = g->Jp[q] * (g->mu[IDX(g, qp, s)] - mu0) / dth;
+      real fd = g->Jm[q] * (mu0 - g->mu[IDX(g, qm, s)]) / dth;
+      real lapmu = (fu - fd) / (r * r * g->J[q] * dth) +
+                   (g->mu[IDX(g, q, sp)] - RC(2) * mu0 + g->mu[IDX(g, q, sm)]) /
+                       (g->J[q] * g->J[q] * dph * dph);
+      real adv = RC(0);
+      if (ch_adv) {
+        /* theta faces carry J u^theta phi, phi faces carry u^phi phi */
+        real Pc = g->J[q] * g->ut[c] * ph;
+        real Pn = g->J[qp] * g->ut[IDX(g, qp, s)] * phi[IDX(g, qp, s)];
+        real Ps = g->J[qm] * g->ut[IDX(g, qm, s)] * phi[IDX(g, qm, s)];
+        real face_n = RC(0.5) * (Pc + Pn), face_s = RC(0.5) * (Ps + Pc);
+        real Qc = g->up[c] * ph;
+        real Qe = g->up[IDX(g, q, sp)] * phi[IDX(g, q, sp)];
+        real Qw = g->up[IDX(g, q, sm)] * phi[IDX(g, q, sm)];
+        real face_e = RC(0.5) * (Qc + Qe), face_w = RC(0.5) * (Qw + Qc);
+        adv = (face_n - face_s) / (r * g->J[q] * dth) + (face_e - face_w) / (g->J[q] * dph);
+      }
+      Lphi[c] = -adv + M * lapmu;
+    }
+  }
+
+  /* 5-7. Boltzmann right-hand side (eq. boltz_tor with every term but d_t f moved right):
+   *   frc = -F^theta (df/dv^theta) - F^phi (df/dv^phi)
+   *   con = +G [ v^phi d(f v^phi)/dv^theta - v^theta d(f v^phi)/dv^phi ],   G = sin(theta)/J
+   *       = +G [ v_j^2 (df/dv^theta) - v_i (d(f v^phi)/dv^phi) ]
+   *   bgk = -(f - f_eq) / tau
+   * with the velocity derivatives from the K^H and K~^H matrices (section II C).             */
+#pragma omp parallel for schedule(static)
+  for (int q = 0; q < nt; ++q)
+    for (int s = 0; s < np; ++s) {
+      size_t c = IDX(g, q, s);
+      real n = g->n[c], ut = g->ut[c], up = g->up[c];
+      real Fth = g->Fth[c], Fph = g->Fph[c];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          int k = 4 * i + j;
+          real dfdvth = RC(0), dfdvph = RC(0), dfvdvph = RC(0);
+          for (int m = 0; m < 4; ++m) {
+            dfdvth += g->K[i][m] * f[FIDX(g, 4 * m + j, q, s)];
+            dfdvph += g->K[j][m] * f[FIDX(g, 4 * i + m, q, s)];
+            dfvdvph += g->Kt[j][m] * f[FIDX(g, 4 * i + m, q, s)];
+          }
+          real fk = f[FIDX(g, k, q, s)];
+          g->frc[FIDX(g, k, q, s)] = -Fth * dfdvth - Fph * dfdvph;
+          g->con[FIDX(g, k, q, s)] = g->G[q] * (g->v[j] * g->v[j] * dfdvth - g->v[i] * dfvdvph);
+          g->bgk[FIDX(g, k, q, s)] = -(fk - feq_one(g, i, j, n, ut, up)) / tau;
+        }
+    }
+
+  /* advection (eq. boltz_tor): -(v_j / J) d_phi f - v_i / (r J) d_theta (J f), conservative
+   * finite differences with UW5 face values taken from the upwind side of each velocity.   */
+#pragma omp parallel for schedule(static)
+  for (int q = 0; q < nt; ++q)
+    for (int s = 0; s < np; ++s)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          int k = 4 * i + j;
+          real vt = g->v[i], vp = g->v[j];
+          /* phi direction: nodal flux h = f */
+          real hp[6];
+          real face_e, face_w;
+          if (vp > 0) { /* h at s-3 .. s+2 */
+            for (int o = 0; o < 6; ++o) hp[o] = f[FIDX(g, k, q, wrap(s - 3 + o, np))];
+            face_e = uw5_face(hp[1], hp[2], hp[3], hp[4], hp[5]);
+            face_w = uw5_face(hp[0], hp[1], hp[2], hp[3], hp[4]);
+          } else { /* h at s-2 .. s+3; the upwind side is s+1 and beyond */
+            for (int o = 0; o < 6; ++o) hp[o] = f[FIDX(g, k, q, wrap(s - 2 + o, np))];
+            face_e = uw5_face(hp[5], hp[4], hp[3], hp[2], hp[1]);
+            face_w = uw5_face(hp[4], hp[3], hp[2], hp[1], hp[0]);
+          }
+          real adv_ph = -(vp / (g->J[q] * dph)) * (face_e - face_w);
+          /* theta direction: nodal flux h = J f */
+          real ht[6];
+          real face_n, face_s;
+          if (vt > 0) {
+            for (int o = 0; o < 6; ++o) {
+              int qq = wrap(q - 3 + o, nt);
+              ht[o] = g->J[qq] * f[FIDX(g, k, qq, s)];
+            }
+            face_n = uw5_face(ht[1], ht[2], ht[3], ht[4], ht[5]);
+            face_s = uw5_face(ht[0], ht[1], ht[2], ht[3], ht[4]);
+          } else {
+            for (int o = 0; o < 6; ++o) {
+              int qq = wrap(q - 2 + o, nt);
+              ht[o] = g->J[qq] * f[FIDX(g, k, qq, s)];
+            }
+            face_n = uw5_face(ht[5], ht[4], ht[3], ht[2], ht[1]);
+            face_s = uw5_face(ht[4], ht[3], ht[2], ht[1], ht[0]);
+          }
+          real adv_th = -(vt / (r * g->J[q] * dth)) * (face_n - face_s);
+          g->adv[FIDX(g, k, q, s)] = adv_ph + adv_th;
+        }
+
+  /* sum of the four terms */
+  const size_t nf = 16 * g->nn;
+#pragma omp parallel for schedule(static)
+  for (size_t x = 0; x < nf; ++x) Lf[x] = g->adv[x] + g->frc[x] + g->con[x] + g->bgk[x];
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Three-stage SSP Runge-Kutta (Shu-Osher form) on the joint state (f, phi):
+ *   y1 = y + dt L(y);  y2 = 3/4 y + 1/4 (y1 + dt L(y1));  y' = 1/3 y + 2/3 (y2 + dt L(y2)). */
+static void ssprk3_step(tlbref_grid* g) {
+  const real dt = g->dt;
+  const real a2 = RC(0.75), b2 = RC(0.25), a3 = RC(1) / RC(3), b3 = RC(2) / RC(3);
+  const size_t nf = 16 * g->nn, nn = g->nn;
+  rhs(g, g->f, g->phi, g->Lf, g->Lphi);
+  for (size_t x = 0; x < nf; ++x) g->f1[x] = g->f[x] + dt * g->Lf[x];
+  for (size_t x = 0; x < nn; ++x) g->phi1[x] = g->phi[x] + dt * g->Lphi[x];
+  rhs(g, g->f1, g->phi1, g->Lf, g->Lphi);
+  for (size_t x = 0; x < nf; ++x) g->f2[x] = a2 * g->f[x] + b2 * (g->f1[x] + dt * g->Lf[x]);
+  for (size_t x = 0; x < nn; ++x)
+    g->phi2[x] = a2 * g->phi[x] + b2 * (g->phi1[x] + dt * g->Lphi[x]);
+  rhs(g, g->f2, g->phi2, g->Lf, g->Lphi);
+  for (size_t x = 0; x < nf; ++x) g->f[x] = a3 * g->f[x] + b3 * (g->f2[x] + dt * g->Lf[x]);
+  for (size_t x = 0; x < nn; ++x)
+    g->phi[x] = a3 * g->phi[x] + b3 * (g->phi2[x] + dt * g->Lphi[x]);
+  g->steps++;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* C interface on host FP64 buffers, mirroring the GPU library's entry points.                 */
+
+static int valid(const tlbref_params* p) {
+  if (!p) return 0;
+  if (!(p->r > 0.0) || !(p->R > p->r)) return 0; /* a = r/R < 1 keeps 1 + a cos > 0 */
+  if (p->n_theta < 1 || p->n_phi < 1) return 0;
+  if (!(p->dt > 0.0) || !(p->tau > 0.0) || !(p->M >= 0.0) || !(p->kappa >= 0.0)) return 0;
+  if (!isfinite(p->A) || !isfinite(p->dt) || !isfinite(p->R)) return 0;
+  return 1;
+}
+
+void tlbref_destroy(tlbref_grid* g);
+
+int tlbref_create(const tlbref_params* p, tlbref_grid** out) {
+  if (!out) return TLBREF_EINVAL;
+  *out = NULL;
+  if (!valid(p)) return TLBREF_EINVAL;
+  tlbref_grid* g = (tlbref_grid*)calloc(1, sizeof(tlbref_grid));
+  if (!g) return TLBREF_ENOMEM;
+  g->p = *p;
+  g->nt = p->n_theta;
+  g->np = p->n_phi;
+  g->nn = (size_t)g->nt * (size_t)g->np;
+  const double pi = acos(-1.0);
+  const double dth = 2.0 * pi / g->nt, dph = 2.0 * pi / g->np;
+  g->r = RC(p->r);
+  g->dth = RC(dth);
+  g->dph = RC(dph);
+  g->A = RC(p->A);
+  g->kappa = RC(p->kappa);
+  g->M = RC(p->M);
+  g->tau = RC(p->tau);
+  g->dt = RC(p->dt);
+  double v[4], w[4], K[4][4], Kt[4][4];
+  velocity_set(v, w, K, Kt);
+  for (int i = 0; i < 4; ++i) {
+    g->v[i] = RC(v[i]);
+    g->w[i] = RC(w[i]);
+    for (int m = 0; m < 4; ++m) {
+      g->K[i][m] = RC(K[i][m]);
+      g->Kt[i][m] = RC(Kt[i][m]);
+    }
+  }
+
+  g->J = (real*)malloc(sizeof(real) * g->nt);
+  g->Jp = (real*)malloc(sizeof(real) * g->nt);
+  g->Jm = (real*)malloc(sizeof(real) * g->nt);
+  g->G = (real*)malloc(sizeof(real) * g->nt);
+  const size_t nn = g->nn, nf = 16 * nn;
+  real** planes[] = {&g->f, &g->f1, &g->f2, &g->Lf, &g->adv, &g->frc, &g->con, &g->bgk};
+  real** scal[] = {&g->phi, &g->phi1, &g->phi2, &g->Lphi, &g->n, &g->ut,
+                   &g->up,  &g->lap,  &g->mu,   &g->Fth,  &g->Fph};
+  int ok = g->J && g->Jp && g->Jm && g->G;
+  for (size_t x = 0; x < sizeof(planes) / sizeof(planes[0]); ++x)
+    ok = ok && (*planes[x] = (real*)calloc(nf, sizeof(real))) != NULL;
+  for (size_t x = 0; x < sizeof(scal) / sizeof(scal[0]); ++x)
+    ok = ok && (*scal[x] = (real*)calloc(nn, sizeof(real))) != NULL;
+  if (!ok) {
+    tlbref_destroy(g);
+    return TLBREF_ENOMEM;
+  }
+  /* geometry rows (appendix A): J = R + r cos theta at the nodes and half-nodes, and the
+   * connection coefficient G = Gamma_{theta phi phi} = sin theta / J */
+  for (int q = 0; q < g->nt; ++q) {
+    double th = q * dth;
+    if (p->flags & TLBREF_FLAT) {
+      g->J[q] = g->Jp[q] = g->Jm[q] = RC(p->R);
+      g->G[q] = RC(0);
+    } else {
+      g->J[q] = RC(p->R + p->r * cos(th));
+      g->Jp[q] = RC(p->R + p->r * cos(th + 0.5 * dth));
+      g->Jm[q] = RC(p->R + p->r * cos(th - 0.5 * dth));
+      g->G[q] = RC(sin(th) / (p->R + p->r * cos(th)));
+    }
+  }
+  *out = g;
+  return TLBREF_OK;
+}
+
+void tlbref_destroy(tlbref_grid* g) {
+  if (!g) return;
+  real* bufs[] = {g->J,    g->Jp,   g->Jm,   g->G,    g->f,   g->f1, g->f2,
+                  g->Lf,   g->adv,  g->frc,  g->con,  g->bgk, g->phi, g->phi1,
+                  g->phi2, g->Lphi, g->n,    g->ut,   g->up,  g->lap, g->mu,
+                  g->Fth,  g->Fph};
+  for (size_t x = 0; x < sizeof(bufs) / sizeof(bufs[0]); ++x) free(bufs[x]);
+  free(g);
+}
+
+/* f == NULL: f = f_eq(n, u) from the given moments; otherwise copy f. phi is always copied. */
+int tlbref_set_state(tlbref_grid* g, const double* f, const double* phi, const double* n,
+                     const double* ut, const double* up) {
+  if (!g || !phi) return TLBREF_EINVAL;
+  if (!f && (!n || !ut || !up)) return TLBREF_EINVAL;
+  for (size_t x = 0; x < g->nn; ++x) g->phi[x] = RC(phi[x]);
+  if (f) {
+    for (size_t x = 0; x < 16 * g->nn; ++x) g->f[x] = RC(f[x]);
+  } else {
+    for (int q = 0; q < g->nt; ++q)
+      for (int s = 0; s < g->np; ++s) {
+        size_t c = IDX(g, q, s);
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j)
+            g->f[FIDX(g, 4 * i + j, q, s)] = feq_one(g, i, j, RC(n[c]), RC(ut[c]), RC(up[c]));
+      }
+  }
+  g->steps = 0;
+  return TLBREF_OK;
+}
+
+int tlbref_get_state(tlbref_grid* g, double* f, double* phi) {
+  if (!g) return TLBREF_EINVAL;
+  if (f)
+    for (size_t x = 0; x < 16 * g->nn; ++x) f[x] = (double)g->f[x];
+  if (phi)
+    for (size_t x = 0; x < g->nn; ++x) phi[x] = (double)g->phi[x];
+  return TLBREF_OK;
+}
+
+int tlbref_step_n(tlbref_grid* g, int64_t nsteps) {
+  if (!g || nsteps < 0) return TLBREF_EINVAL;
+  for (int64_t t = 0; t < nsteps; ++t) ssprk3_step(g);
+  return TLBREF_OK;
+}
+
+/* Moments of the current state; mu (nullable) is the chemical potential of eq. mu. */
+int tlbref_get_moments(tlbref_grid* g, double* n, double* ut, double* up, double* phi,
+                       double* mu) {
+  if (!g) return TLBREF_EINVAL;
+  /* one right-hand-side evaluation fills the moment and mu arrays for the current state */
+  rhs(g, g->f, g->phi, g->Lf, g->Lphi);
+  for (size_t x = 0; x < g->nn; ++x) {
+    if (n) n[x] = (double)g->n[x];
+    if (ut) ut[x] = (double)g->ut[x];
+    if (up) up[x] = (double)g->up[x];
+    if (phi) phi[x] = (double)g->phi[x];
+    if (mu) mu[x] = (double)g->mu[x];
+  }
+  return TLBREF_OK;
+}
+
+/* Conservation diagnostics, always summed in double in a fixed order:
+ * out[0] = mass = sum r J dtheta dphi n, out[1] = the same weighted sum of phi,
+ * out[2] = number of non-finite values in (f, phi). */
+int tlbref_invariants(tlbref_grid* g, double out[3]) {
+  if (!g || !out) return TLBREF_EINVAL;
+  const double pi = acos(-1.0);
+  const double dth = 2.0 * pi / g->nt, dph = 2.0 * pi / g->np;
+  double mass = 0.0, phisum = 0.0, bad = 0.0;
+  for (int q = 0; q < g->nt; ++q) {
+    double J = (g->p.flags & TLBREF_FLAT) ? g->p.R : g->p.R + g->p.r * cos(q * dth);
+    double area = g->p.r * J * dth * dph;
+    double rowm = 0.0, rowp = 0.0;
+    for (int s = 0; s < g->np; ++s) {
+      size_t c = IDX(g, q, s);
+      double n = 0.0;
+      for (int k = 0; k < 16; ++k) {
+        double fk = (double)g->f[(size_t)k * g->nn + c];
+        if (!isfinite(fk)) bad += 1.0;
+        n += fk;
+      }
+      double ph = (double)g->phi[c];
+      if (!isfinite(ph)) bad += 1.0;
+      rowm += n;
+      rowp += ph;
+    }
+    mass += area * rowm;
+    phisum += area * rowp;
+  }
+  out[0] = mass;
+  out[1] = phisum;
+  out[2] = bad;
+  return bad > 0 ? TLBREF_ENONFINITE : TLBREF_OK;
+}
+
+/* Right-hand side of an arbitrary state, with each Boltzmann term returned separately
+ * (any output pointer may be NULL).  mu / lap / F are the intermediates of the same call. */
+int tlbref_rhs_terms(tlbref_grid* g, const double* f, const double* phi, double* Lf,
+                     double* Lphi, double* adv, double* frc, double* con, double* bgk,
+                     double* mu, double* lap, double* Fth, double* Fph) {
+  if (!g || !f || !phi) return TLBREF_EINVAL;
+  for (size_t x = 0; x < 16 * g->nn; ++x) g->f1[x] = RC(f[x]);
+  for (size_t x = 0; x < g->nn; ++x) g->phi1[x] = RC(phi[x]);
+  rhs(g, g->f1, g->phi1, g->Lf, g->Lphi);
+  for (size_t x = 0; x < 16 * g->nn; ++x) {
+    if (Lf) Lf[x] = (double)g->Lf[x];
+    if (adv) adv[x] = (double)g->adv[x];
+    if (frc) frc[x] = (double)g->frc[x];
+    if (con) con[x] = (double)g->con[x];
+    if (bgk) bgk[x] = (double)g->bgk[x];
+  }
+  for (size_t x = 0; x < g->nn; ++x) {
+    if (Lphi) Lphi[x] = (double)g->Lphi[x];
+    if (mu) mu[x] = (double)g->mu[x];
+    if (lap) lap[x] = (double)g->lap[x];
+    if (Fth) Fth[x] = (double)g->Fth[x];
+    if (Fph) Fph[x] = (double)g->Fph[x];
+  }
+  return TLBREF_OK;
+}
+
+/* Constants of the velocity set in double: v[4], w[4], K[16], Kt[16] (row-major, K[i][m]). */
+void tlbref_velocity_set(double v[4], double w[4], double K[16], double Kt[16]) {
+  double K2[4][4], Kt2[4][4];
+  velocity_set(v, w, K2, Kt2);
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m) {
+      K[4 * i + m] = K2[i][m];
+      Kt[4 * i + m] = Kt2[i][m];
+    }
+}
+
+/* Geometry rows as used by the step: J, J at +/- half a cell, G (nullable outputs). */
+int tlbref_geometry(tlbref_grid* g, double* J, double* Jp, double* Jm, double* G) {
+  if (!g) return TLBREF_EINVAL;
+  for (int q = 0; q < g->nt; ++q) {
+    if (J) J[q] = (double)g->J[q];
+    if (Jp) Jp[q] = (double)g->Jp[q];
+    if (Jm) Jm[q] = (double)g->Jm[q];
+    if (G) G[q] = (double)g->G[q];
+  }
+  return TLBREF_OK;
+}
+
+int64_t tlbref_steps(const tlbref_grid* g) { return g ? g->steps : -1; }
+
+int tlbref_real_bytes(void) { return (int)sizeof(real); }

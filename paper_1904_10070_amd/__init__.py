@@ -1,0 +1,10 @@
+"""MI355X-native vielbein lattice Boltzmann step for binary fluids on a periodic torus.
+
+The step itself runs in the HIP kernels of libtlb.so (C interface: include/tlb.h);
+`binding.TorusGrid` marshals torch device buffers and streams into it, and `inputs` builds the
+seeded synthetic initial conditions.
+"""
+from . import inputs  # noqa: F401
+from .binding import TorusGrid, load_library, TlbError, FLAT, CH_NO_ADVECTION  # noqa: F401
+
+__all__ = ["TorusGrid", "load_library", "TlbError", "FLAT", "CH_NO_ADVECTION", "inputs"]

@@ -1,0 +1,180 @@
+"""Thin ctypes binding of the C interface in include/tlb.h.
+
+Argument marshalling only: PyTorch provides the device buffers and the stream, and every step
+of the method runs in the HIP kernels of libtlb.so.  There is no fallback: if the library has
+not been built, or no GPU is visible, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtlb.so")
+
+TLB_OK = 0
+TLB_EINVAL = -1
+TLB_ENOMEM = -2
+TLB_EHIP = -3
+TLB_ENONFINITE = -4
+
+FLAT = 1
+CH_NO_ADVECTION = 2
+
+EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
+            "tlb_get_state", "tlb_invariants", "tlb_destroy", "tlb_last_error")
+
+
+class TlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_double), ("R", ctypes.c_double),
+                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("A", ctypes.c_double), ("kappa", ctypes.c_double), ("M", ctypes.c_double),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p * 3), ("phi", ctypes.c_void_p * 3)]
+
+
+_LIB = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libtlb.so and declare its signatures; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it first (python -m paper_1904_10070_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.tlb_create_torus_grid.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Buffers), vp,
+                                          ctypes.POINTER(vp)]
+    lib.tlb_create_torus_grid.restype = i32
+    lib.tlb_set_state.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tlb_set_state.restype = i32
+    lib.tlb_step_n.argtypes = [vp, i64]
+    lib.tlb_step_n.restype = i32
+    lib.tlb_get_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tlb_get_moments.restype = i32
+    lib.tlb_get_state.argtypes = [vp, vp, vp]
+    lib.tlb_get_state.restype = i32
+    lib.tlb_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.tlb_invariants.restype = i32
+    lib.tlb_destroy.argtypes = [vp]
+    lib.tlb_destroy.restype = None
+    lib.tlb_last_error.argtypes = []
+    lib.tlb_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(lib, rc, what):
+    if rc != TLB_OK:
+        raise TlbError(rc, f"{what}: {lib.tlb_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class TorusGrid:
+    """A torus grid whose state lives in torch-owned device memory and is stepped by libtlb.
+
+    params: an object with the fields of tlb_params (e.g. inputs.TorusParams).
+    precision: 32 or 64.  stream: a torch.cuda.Stream (default: the current stream).
+    """
+
+    def __init__(self, params, precision=64, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the torus step runs only in the HIP kernels")
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.precision = precision
+        self.params = params
+        nt, np_ = int(params.n_theta), int(params.n_phi)
+        self.shape = (nt, np_)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # state copies: 0 = current state, 1 and 2 = Runge-Kutta stage scratch
+        self.f = [torch.zeros((16, nt, np_), dtype=self.dtype, device=self.device) for _ in range(3)]
+        self.phi = [torch.zeros((nt, np_), dtype=self.dtype, device=self.device) for _ in range(3)]
+        p = Params(params.r, params.R, nt, np_, params.A, params.kappa, params.M, params.tau,
+                   params.dt, precision, int(getattr(params, "flags", 0)))
+        b = Buffers()
+        for i in range(3):
+            b.f[i] = self.f[i].data_ptr()
+            b.phi[i] = self.phi[i].data_ptr()
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check(self.lib, self.lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b),
+                                                        ctypes.c_void_p(self.stream.cuda_stream),
+                                                        ctypes.byref(h)), "tlb_create_torus_grid")
+        self._h = h
+
+    # -- helpers ------------------------------------------------------------------------------
+    def _dev(self, x, shape):
+        t = self.torch.as_tensor(np.asarray(x) if not isinstance(x, self.torch.Tensor) else x)
+        t = t.to(device=self.device, dtype=self.dtype).contiguous()
+        assert tuple(t.shape) == shape, (tuple(t.shape), shape)
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.tlb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C interface ------------------------------------------------------------------------
+    def set_state(self, phi, n=None, u_theta=None, u_phi=None, f=None):
+        with self.torch.cuda.stream(self.stream):
+            phi_t = self._dev(phi, self.shape)
+            if f is not None:
+                f_t = self._dev(f, (16,) + self.shape)
+                args = (f_t, phi_t, None, None, None)
+            else:
+                args = (None, phi_t, self._dev(n, self.shape), self._dev(u_theta, self.shape),
+                        self._dev(u_phi, self.shape))
+            _check(self.lib, self.lib.tlb_set_state(self._h, *(_ptr(a) for a in args)),
+                   "tlb_set_state")
+            self._keep = args  # keep the inputs alive until the stream has consumed them
+
+    def step(self, nsteps):
+        _check(self.lib, self.lib.tlb_step_n(self._h, int(nsteps)), "tlb_step_n")
+
+    def moments(self, with_mu=True):
+        out = {k: self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+               for k in ("n", "u_theta", "u_phi", "phi")}
+        out["mu"] = (self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+                     if with_mu else None)
+        _check(self.lib, self.lib.tlb_get_moments(self._h, *(_ptr(out[k]) for k in
+                                                             ("n", "u_theta", "u_phi", "phi", "mu"))),
+               "tlb_get_moments")
+        return out
+
+    def get_state(self):
+        f = self.torch.empty((16,) + self.shape, dtype=self.dtype, device=self.device)
+        phi = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        _check(self.lib, self.lib.tlb_get_state(self._h, _ptr(f), _ptr(phi)), "tlb_get_state")
+        return f, phi
+
+    def invariants(self, check=False):
+        out = (ctypes.c_double * 3)()
+        rc = self.lib.tlb_invariants(self._h, out)
+        if rc not in (TLB_OK, TLB_ENONFINITE) or (check and rc != TLB_OK):
+            _check(self.lib, rc, "tlb_invariants")
+        return float(out[0]), float(out[1]), int(out[2])

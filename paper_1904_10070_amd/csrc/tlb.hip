@@ -1,0 +1,808 @@
+// tlb.hip -- MI355X (gfx950, CDNA4) implementation of the vielbein lattice Boltzmann
+// binary-fluid step on a periodic torus (Ambrus, Busuioc, Wagner, Paillusson, Kusumaatmaja,
+// arXiv:1904.10070) behind the C interface of include/tlb.h.
+//
+// One time step = three launches of one fused stage kernel (three-stage SSP Runge-Kutta).
+// Each launch evaluates the whole right-hand side of the semi-discrete system for a tile of
+// 64 (phi) x 4 (theta) nodes and writes the Runge-Kutta combination:
+//   * order parameter tile with a 2-node halo -> LDS; chemical potential mu (eq. mu, with the
+//     surface Laplace-Beltrami operator) on the tile and its cross-shaped 1-node ring -> LDS;
+//   * the 16 populations stream one at a time through a double-buffered LDS tile with a
+//     3-node halo: each thread keeps its node's f_k and accumulates the upwind (UW5) flux
+//     difference along phi and theta (eq. boltz_tor advection, metric factors r and J);
+//     threads owning a ring node accumulate that node's moments for the CH flux;
+//   * per node: moments, f_eq (eq. feq), BGK, the velocity-space force and connection terms
+//     through the K^H matrix (section II C), the phi grad mu interface force (eq. pbin), the
+//     Cahn-Hilliard right-hand side (eq. CH), and the Runge-Kutta combine -> coalesced stores.
+// Wavefront = one 64-node row of the tile, so per-row geometry is wavefront-uniform.
+// Tiles are numbered so that each of the 8 XCDs owns a contiguous band of theta rows, which
+// keeps the theta halos of neighbouring tiles in the same L2.
+//
+// Discretisation readings (the paper defers its numerical scheme to supplementary material):
+// conservative finite differences with fifth-order upwind face values for the advection,
+// second-order central flux form for Cahn-Hilliard, SSP-RK3 in time, potential-form force
+// n F = -phi grad mu with central differences, u = sum f v / n.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "tlb.h"
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// error reporting
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define TLB_HIP_CHECK(call)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(TLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// velocity space (section II C)
+
+// Q = 4 Gauss-Hermite velocity set (eq. vmatrix) and weights w = (3 -/+ sqrt 6)/12, with the
+// irrational roots written out as literals so that every constant below folds at compile time.
+constexpr double SQRT6 = 2.449489742783178098197284074705891391966;
+constexpr double VOUT = 2.334414218338977239317512267210362194489;  // sqrt(3 + sqrt 6)
+constexpr double VIN = 0.7419637843027258576485135967263602248295;  // sqrt(3 - sqrt 6)
+
+__host__ __device__ constexpr double vel(int i) {
+  return i == 0 ? -VOUT : i == 1 ? -VIN : i == 2 ? VIN : VOUT;
+}
+__host__ __device__ constexpr double wgt(int i) {
+  return (i == 0 || i == 3) ? (3.0 - SQRT6) / 12.0 : (3.0 + SQRT6) / 12.0;
+}
+// probabilists' Hermite polynomials He_0..He_4, written out
+__host__ __device__ constexpr double hermite_e(int l, double x) {
+  return l == 0 ? 1.0 : l == 1 ? x : l == 2 ? x * x - 1.0 : l == 3 ? x * x * x - 3.0 * x
+       : x * x * x * x - 6.0 * x * x + 3.0;
+}
+// velocity-derivative kernel K^H_{im} = -w_i sum_{l<Q} He_{l+1}(v_i) He_l(v_m) / l!
+__host__ __device__ constexpr double kh(int i, int m) {
+  return -wgt(i) * (hermite_e(1, vel(i)) * hermite_e(0, vel(m)) +
+                    hermite_e(2, vel(i)) * hermite_e(1, vel(m)) +
+                    hermite_e(3, vel(i)) * hermite_e(2, vel(m)) / 2.0 +
+                    hermite_e(4, vel(i)) * hermite_e(3, vel(m)) / 6.0);
+}
+
+template <int I>
+using ic = std::integral_constant<int, I>;
+// compile-time loop: fn(ic<B>{}), fn(ic<B+1>{}), ..., fn(ic<E-1>{})
+template <int B, int E, class F>
+__host__ __device__ __forceinline__ void static_for(F&& fn) {
+  if constexpr (B < E) {
+    fn(ic<B>{});
+    static_for<B + 1, E>(static_cast<F&&>(fn));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// tile geometry of the stage kernel
+constexpr int TX = 64;           // nodes along phi per tile = wavefront width
+constexpr int TY = 4;            // nodes along theta per tile = wavefronts per block
+constexpr int HX = 3, HY = 3;    // population halo (UW5 needs 3 upwind, 2 downwind)
+constexpr int LX = TX + 2 * HX;  // 70
+constexpr int LY = TY + 2 * HY;  // 10
+constexpr int NT = TX * TY;      // 256 threads
+constexpr int FSLOTS = (LX * LY + NT - 1) / NT;  // 3 loads per thread per population
+constexpr int PX = TX + 4, PY = TY + 4;          // order-parameter tile with a 2-node halo
+constexpr int PSLOTS = (PX * PY + NT - 1) / NT;  // 3
+constexpr int NRING = 2 * TX + 2 * TY;           // cross-shaped ring of 1 node
+static_assert(NRING <= NT, "ring nodes must fit one per thread");
+
+// UW5 flux difference (face_{+1/2} - face_{-1/2}) for a positive velocity, offsets -3..+2;
+// the negative-velocity stencil is its mirror image with the sign flipped, offsets -2..+3.
+__host__ __device__ constexpr double uw5p(int o) {
+  return o == -3 ? -2.0 / 60 : o == -2 ? 15.0 / 60 : o == -1 ? -60.0 / 60
+       : o == 0 ? 20.0 / 60 : o == 1 ? 30.0 / 60 : o == 2 ? -3.0 / 60 : 0.0;
+}
+__host__ __device__ constexpr double uw5m(int o) { return -uw5p(-o); }
+
+// Per theta-row coefficients (one record per row q), all derived on the host in FP64.
+template <typename T>
+struct RowCoef {
+  T bth_p[6];    // theta advection, v > 0: uw5p(o) J_{q+o} / (r J_q dtheta), o = -3..2
+  T bth_m[6];    // theta advection, v < 0: uw5m(o) J_{q+o} / (r J_q dtheta), o = -2..3
+  T inv_Jdph;    // 1 / (J_q dphi)
+  T J;           // J_q = R + r cos theta_q
+  T G;           // sin theta_q / J_q (connection coefficient)
+  T lap_n;       // J_{q+1/2} / (r^2 J_q dtheta^2)
+  T lap_s;       // J_{q-1/2} / (r^2 J_q dtheta^2)
+  T lap_p;       // 1 / (J_q^2 dphi^2)
+  T inv_2Jdph;   // 1 / (2 J_q dphi)
+  T inv_2rJdth;  // 1 / (2 r J_q dtheta)
+};
+
+template <typename T>
+struct Consts {
+  T A, kappa, M, inv_tau, inv_2rdth, dt;
+  int ch_adv;
+};
+
+template <typename T>
+struct StageArgs {
+  const T* fin;    // stage input populations (read with halos)
+  const T* phin;   // stage input order parameter
+  const T* f0;     // y^n populations (read at the node only; may alias fout)
+  const T* phi0;
+  T* fout;
+  T* phiout;
+  const RowCoef<T>* rows;
+  int nt, np, ntx, nty;
+  long long plane;  // nt * np
+  T a0, b1;         // out = a0 * y^n + b1 * (y_s + dt L(y_s))
+  int has_y0;       // a0 != 0
+  Consts<T> c;
+};
+
+__device__ __forceinline__ int wrapi(int x, int n) {
+  int m = x % n;
+  return m < 0 ? m + n : m;
+}
+
+// Block -> tile mapping: consecutive hardware blocks go round-robin over the 8 XCDs; give
+// XCD x the contiguous tile range [start_x, start_x + count_x) in row-major tile order.
+__host__ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
+  const int xcd = b & 7, local = b >> 3;
+  const int full = nblk >> 3, rem = nblk & 7;
+  return xcd < rem ? xcd * (full + 1) + local : rem * (full + 1) + (xcd - rem) * full + local;
+}
+
+// Empty register-to-register asm: the value must exist at this point of the program, so its
+// computation cannot be moved past it (used to stop arithmetic from sinking across barriers).
+__device__ __forceinline__ void pin_reg(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_reg(double& x) { asm volatile("" : "+v"(x)); }
+
+// chemical potential (eq. mu) at local node (y, x) in [-1, TY] x [-1, TX] of the phi tile
+template <typename T>
+__device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>& rc, T A,
+                                   T kappa) {
+  const int c = (y + 2) * PX + (x + 2);
+  const T ph = sPhi[c];
+  const T lap = rc.lap_n * (sPhi[c + PX] - ph) - rc.lap_s * (ph - sPhi[c - PX]) +
+                rc.lap_p * (sPhi[c + 1] - T(2) * ph + sPhi[c - 1]);
+  return A * ph * (ph * ph - T(1)) - kappa * lap;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
+  __shared__ T sF[2][LY * LX];
+  __shared__ T sPhi[PY * PX];
+  __shared__ T sMu[(TY + 2) * (TX + 2)];
+  __shared__ T sPt[(TY + 2) * TX];  // J u^theta phi on the tile and the rows above/below
+  __shared__ T sPp[TY * (TX + 2)];  // u^phi phi on the tile and the columns left/right
+
+  const int tid = threadIdx.x;
+  const int lx = tid & (TX - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform row
+  const int nt = a.nt, np = a.np;
+  const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
+  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
+  const int q0 = ty * TY, s0 = tx * TX;
+  const int q = q0 + ly, s = s0 + lx;
+  const bool active = (q < nt) && (s < np);
+  const int qw = wrapi(q, nt);
+  const RowCoef<T>& rc = a.rows[qw];
+
+  // ---- order parameter tile with a 2-node halo (periodic wrap in both angles)
+#pragma unroll
+  for (int i = 0; i < PSLOTS; ++i) {
+    const int l = tid + i * NT;
+    if (l < PX * PY) {
+      const int yy = l / PX, xx = l - yy * PX;
+      const int gq = wrapi(q0 + yy - 2, nt), gs = wrapi(s0 + xx - 2, np);
+      sPhi[l] = a.phin[(long long)gq * np + gs];
+    }
+  }
+  // ---- population tile addresses (the same for every population), first prefetch
+  int off[FSLOTS];
+  bool ok[FSLOTS];
+#pragma unroll
+  for (int i = 0; i < FSLOTS; ++i) {
+    const int l = tid + i * NT;
+    ok[i] = l < LX * LY;
+    const int yy = l / LX, xx = l - yy * LX;
+    off[i] = ok[i] ? wrapi(q0 + yy - HY, nt) * np + wrapi(s0 + xx - HX, np) : 0;
+  }
+  T pre[FSLOTS];
+#pragma unroll
+  for (int i = 0; i < FSLOTS; ++i) pre[i] = ok[i] ? a.fin[off[i]] : T(0);
+
+  // ---- ring role: one cross-ring node per thread for tid < NRING
+  int ry, rx;
+  if (tid < TX) { ry = -1; rx = tid; }
+  else if (tid < 2 * TX) { ry = TY; rx = tid - TX; }
+  else if (tid < 2 * TX + TY) { ry = tid - 2 * TX; rx = -1; }
+  else { ry = tid - 2 * TX - TY; rx = TX; }
+  const bool ring = tid < NRING;
+  if (!ring) { ry = 0; rx = 0; }
+  const RowCoef<T>& rrc = a.rows[wrapi(q0 + ry, nt)];
+
+  __syncthreads();
+
+  // ---- chemical potential on the tile and the ring
+  sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
+  if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
+
+  // ---- stream the 16 populations through LDS
+  T f[16], adv[16];
+  T rn = T(0), rut = T(0), rup = T(0);
+  const int cN = (ly + HY) * LX + lx + HX;  // this node in the population tile
+  const int cR = (ry + HY) * LX + rx + HX;  // the ring node
+  const T inv_Jdph = rc.inv_Jdph;
+
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int i = k >> 2, j = k & 3;
+    T* buf = sF[k & 1];
+#pragma unroll
+    for (int sl = 0; sl < FSLOTS; ++sl)
+      if (ok[sl]) buf[tid + sl * NT] = pre[sl];
+    __syncthreads();
+    if constexpr (k < 15) {
+      const T* src = a.fin + (long long)(k + 1) * a.plane;
+#pragma unroll
+      for (int sl = 0; sl < FSLOTS; ++sl) pre[sl] = ok[sl] ? src[off[sl]] : T(0);
+    }
+    f[k] = buf[cN];
+    // phi direction: sum_o uw5(o) f_{s+o}, upwind side by the sign of v_j
+    T dph = T(0);
+    if constexpr (j >= 2) {
+      static_for<-3, 3>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        dph += T(uw5p(o)) * buf[cN + o];
+      });
+    } else {
+      static_for<-2, 4>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        dph += T(uw5m(o)) * buf[cN + o];
+      });
+    }
+    // theta direction: sum_o uw5(o) J_{q+o} / (r J_q dtheta) f_{q+o}
+    T dth = T(0);
+    if constexpr (i >= 2) {
+      static_for<-3, 3>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        dth += rc.bth_p[o + 3] * buf[cN + o * LX];
+      });
+    } else {
+      static_for<-2, 4>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        dth += rc.bth_m[o + 2] * buf[cN + o * LX];
+      });
+    }
+    adv[k] = -(T(vel(i)) * dth + (T(vel(j)) * inv_Jdph) * dph);
+    if (ring) {
+      const T fr = buf[cR];
+      rn += fr;
+      rut += T(vel(i)) * fr;
+      rup += T(vel(j)) * fr;
+    }
+    // keep the arithmetic of this population here: without the pin the compiler sinks it to
+    // the end of the kernel and holds every stencil value of all 16 populations live
+    pin_reg(adv[k]);
+    pin_reg(f[k]);
+    pin_reg(rn);
+    pin_reg(rut);
+    pin_reg(rup);
+  });
+
+  // ---- moments at the node; CH fluxes of the tile and the ring
+  T n = T(0), nut = T(0), nup = T(0);
+  static_for<0, 4>([&](auto ic_) {
+    constexpr int i = decltype(ic_)::value;
+    const T row = (f[4 * i] + f[4 * i + 1]) + (f[4 * i + 2] + f[4 * i + 3]);
+    const T col = (f[i] + f[4 + i]) + (f[8 + i] + f[12 + i]);
+    n += row;
+    nut += T(vel(i)) * row;
+    nup += T(vel(i)) * col;
+  });
+  const T inv_n = T(1) / n;
+  const T ut = nut * inv_n, up = nup * inv_n;
+  const T phc = sPhi[(ly + 2) * PX + lx + 2];
+  sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
+  sPp[ly * (TX + 2) + lx + 1] = up * phc;
+  if (ring) {
+    const T phr = sPhi[(ry + 2) * PX + rx + 2];
+    const T inv_rn = T(1) / rn;
+    if (ry < 0 || ry >= TY) sPt[(ry + 1) * TX + rx] = rrc.J * (rut * inv_rn) * phr;
+    else sPp[ry * (TX + 2) + rx + 1] = (rup * inv_rn) * phr;
+  }
+  __syncthreads();
+
+  // ---- interface force n F = -phi grad mu and the Cahn-Hilliard right-hand side
+  const int cm = (ly + 1) * (TX + 2) + lx + 1;
+  const T mu_c = sMu[cm], mu_n = sMu[cm + TX + 2], mu_s = sMu[cm - (TX + 2)];
+  const T mu_e = sMu[cm + 1], mu_w = sMu[cm - 1];
+  const T Fth = -phc * (mu_n - mu_s) * a.c.inv_2rdth * inv_n;
+  const T Fph = -phc * (mu_e - mu_w) * rc.inv_2Jdph * inv_n;
+  const T lapmu = rc.lap_n * (mu_n - mu_c) - rc.lap_s * (mu_c - mu_s) +
+                  rc.lap_p * (mu_e - T(2) * mu_c + mu_w);
+  T Lphi = a.c.M * lapmu;
+  if (a.c.ch_adv) {
+    const int ct = (ly + 1) * TX + lx, cp = ly * (TX + 2) + lx + 1;
+    Lphi -= (sPt[ct + TX] - sPt[ct - TX]) * rc.inv_2rJdth +
+            (sPp[cp + 1] - sPp[cp - 1]) * rc.inv_2Jdph;
+  }
+
+  const long long node = (long long)qw * np + (s < np ? s : 0);
+  const T dt = a.c.dt, a0 = a.a0, b1 = a.b1;
+  const bool y0 = a.has_y0;
+  if (active) {
+    const T ys = phc + dt * Lphi;
+    a.phiout[node] = y0 ? a0 * a.phi0[node] + b1 * ys : ys;
+  }
+
+  // ---- equilibrium (eq. feq) as a cubic in xi = v.u:
+  //      f_eq = n w_i w_j [c0 (1 + xi) + xi^2/2 + xi^3/6],  c0 = 1 - u^2/2
+  // ---- velocity derivatives (section II C): (df/dv^theta)_ij = sum_m K_im f_mj,
+  //      (df/dv^phi)_ij = sum_m K_jm f_im, (d(f v^phi)/dv^phi)_ij = sum_m K_jm v_m f_im, so the
+  //      force and connection terms combine into
+  //      S_ij = (G v_j^2 - F^theta) sum_m K_im f_mj - sum_m K_jm (F^phi + G v_i v_m) f_im.
+  const T c0 = T(1) - T(0.5) * (ut * ut + up * up);
+  const T G = rc.G;
+  T g[16];
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int i = k >> 2, m = k & 3;
+    g[k] = (Fph + G * T(vel(i) * vel(m))) * f[k];
+  });
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int i = k >> 2, j = k & 3;
+    T dvt = T(0), dvp = T(0);
+    static_for<0, 4>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      dvt += T(kh(i, m)) * f[4 * m + j];
+      dvp += T(kh(j, m)) * g[4 * i + m];
+    });
+    const T xi = T(vel(i)) * ut + T(vel(j)) * up;
+    const T poly = c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
+    const T feq = (n * T(wgt(i) * wgt(j))) * poly;
+    const T L = adv[k] + (G * T(vel(j) * vel(j)) - Fth) * dvt - dvp + (feq - f[k]) * a.c.inv_tau;
+    const T ys = f[k] + dt * L;
+    if (active) {
+      T* dst = a.fout + k * a.plane + node;
+      *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------------------
+// f = f_eq(n, u) (eq. feq), one thread per node
+template <typename T>
+__global__ __launch_bounds__(256) void tlb_init_feq_kernel(T* f, const T* n, const T* ut,
+                                                          const T* up, long long plane) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= plane) return;
+  const T nn = n[x], a = ut[x], b = up[x];
+  const T c0 = T(1) - T(0.5) * (a * a + b * b);
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int i = k >> 2, j = k & 3;
+    const T xi = T(vel(i)) * a + T(vel(j)) * b;
+    f[k * plane + x] = (nn * T(wgt(i) * wgt(j))) * (c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0))));
+  });
+}
+
+// moments and chemical potential of a state, one thread per node
+template <typename T>
+__global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* phi, T* n_out,
+                                                         T* ut_out, T* up_out, T* phi_out,
+                                                         T* mu_out, const RowCoef<T>* rows,
+                                                         int nt, int np, T A, T kappa) {
+  const long long plane = (long long)nt * np;
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= plane) return;
+  const int q = (int)(x / np), s = (int)(x - (long long)q * np);
+  T n = T(0), nut = T(0), nup = T(0);
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const T fk = f[k * plane + x];
+    n += fk;
+    nut += T(vel(k >> 2)) * fk;
+    nup += T(vel(k & 3)) * fk;
+  });
+  if (n_out) n_out[x] = n;
+  if (ut_out) ut_out[x] = nut / n;
+  if (up_out) up_out[x] = nup / n;
+  const T ph = phi[x];
+  if (phi_out) phi_out[x] = ph;
+  if (mu_out) {
+    const RowCoef<T>& rc = rows[q];
+    const int qn = q + 1 == nt ? 0 : q + 1, qs = q == 0 ? nt - 1 : q - 1;
+    const int se = s + 1 == np ? 0 : s + 1, sw = s == 0 ? np - 1 : s - 1;
+    const T lap = rc.lap_n * (phi[(long long)qn * np + s] - ph) -
+                  rc.lap_s * (ph - phi[(long long)qs * np + s]) +
+                  rc.lap_p * (phi[(long long)q * np + se] - T(2) * ph + phi[(long long)q * np + sw]);
+    mu_out[x] = A * ph * (ph * ph - T(1)) - kappa * lap;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// conservation diagnostics in FP64: per-block partials in a fixed order, then one block
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, const T* phi,
+                                                                const double* area, int nt,
+                                                                int np, int rows_per_block,
+                                                                double* partial) {
+  __shared__ double s[3][RED_THREADS / 64];
+  const int q_begin = blockIdx.x * rows_per_block;
+  const int q_end = min(nt, q_begin + rows_per_block);
+  const long long plane = (long long)nt * np;
+  double m = 0.0, p = 0.0, bad = 0.0;
+  for (int q = q_begin; q < q_end; ++q) {
+    double rm = 0.0, rp = 0.0;
+    for (int s0 = threadIdx.x; s0 < np; s0 += RED_THREADS) {
+      const long long x = (long long)q * np + s0;
+      double n = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double fk = (double)f[k * plane + x];
+        bad += isfinite(fk) ? 0.0 : 1.0;
+        n += fk;
+      }
+      const double ph = (double)phi[x];
+      bad += isfinite(ph) ? 0.0 : 1.0;
+      rm += n;
+      rp += ph;
+    }
+    m += area[q] * rm;
+    p += area[q] * rp;
+  }
+  m = wave_sum(m);
+  p = wave_sum(p);
+  bad = wave_sum(bad);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s[0][w] = m;
+    s[1][w] = p;
+    s[2][w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int i = 0; i < RED_THREADS / 64; ++i) t += s[threadIdx.x][i];
+    partial[3 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void tlb_reduce_final_kernel(const double* partial,
+                                                                      int nblocks,
+                                                                      double* out) {
+  __shared__ double s[3][RED_THREADS / 64];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+    for (int c = 0; c < 3; ++c) v[c] += partial[3 * b + c];
+  for (int c = 0; c < 3; ++c) v[c] = wave_sum(v[c]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 3; ++c) s[c][w] = v[c];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int i = 0; i < RED_THREADS / 64; ++i) t += s[threadIdx.x][i];
+    out[threadIdx.x] = t;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host side: per-launch constants and the per-row geometry (appendix A), derived in FP64
+template <typename T>
+Consts<T> make_consts(const tlb_params& p) {
+  Consts<T> c{};
+  const double dth = 2.0 * M_PI / p.n_theta;
+  c.A = T(p.A);
+  c.kappa = T(p.kappa);
+  c.M = T(p.M);
+  c.inv_tau = T(1.0 / p.tau);
+  c.inv_2rdth = T(1.0 / (2.0 * p.r * dth));
+  c.dt = T(p.dt);
+  c.ch_adv = (p.flags & TLB_CH_NO_ADVECTION) ? 0 : 1;
+  return c;
+}
+
+template <typename T>
+void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
+  const int nt = p.n_theta;
+  const double dth = 2.0 * M_PI / nt, dph = 2.0 * M_PI / p.n_phi;
+  const bool flat = p.flags & TLB_FLAT;
+  auto Jat = [&](double th) { return flat ? p.R : p.R + p.r * std::cos(th); };
+  for (int q = 0; q < nt; ++q) {
+    const double th = q * dth;
+    const double J = Jat(th);
+    RowCoef<T>& rc = rows[q];
+    for (int o = -3; o <= 2; ++o) {
+      const int qq = ((q + o) % nt + nt) % nt;
+      rc.bth_p[o + 3] = T(uw5p(o) * Jat(qq * dth) / (p.r * J * dth));
+    }
+    for (int o = -2; o <= 3; ++o) {
+      const int qq = ((q + o) % nt + nt) % nt;
+      rc.bth_m[o + 2] = T(uw5m(o) * Jat(qq * dth) / (p.r * J * dth));
+    }
+    rc.inv_Jdph = T(1.0 / (J * dph));
+    rc.J = T(J);
+    rc.G = T(flat ? 0.0 : std::sin(th) / J);
+    rc.lap_n = T(Jat(th + 0.5 * dth) / (p.r * p.r * J * dth * dth));
+    rc.lap_s = T(Jat(th - 0.5 * dth) / (p.r * p.r * J * dth * dth));
+    rc.lap_p = T(1.0 / (J * J * dph * dph));
+    rc.inv_2Jdph = T(1.0 / (2.0 * J * dph));
+    rc.inv_2rJdth = T(1.0 / (2.0 * p.r * J * dth));
+    area[q] = p.r * J * dth * dph;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+struct tlb_grid {
+  tlb_params p;
+  void* f[3];
+  void* phi[3];
+  hipStream_t stream;
+  void* rows;       // RowCoef<T>[nt]
+  double* area;     // [nt]
+  double* partial;  // [3 * red_blocks + 3]
+  int red_blocks, rows_per_block;
+  size_t elem;
+};
+
+namespace {
+
+template <typename T>
+int32_t launch_stage(tlb_grid* g, int stage) {
+  StageArgs<T> a{};
+  const int src = stage == 1 ? 0 : stage - 1;  // stage 1 reads y^n, 2 reads y1, 3 reads y2
+  const int dst = stage == 3 ? 0 : stage;      // stage 3 writes y^{n+1} over y^n
+  a.fin = static_cast<const T*>(g->f[src]);
+  a.phin = static_cast<const T*>(g->phi[src]);
+  a.f0 = static_cast<const T*>(g->f[0]);
+  a.phi0 = static_cast<const T*>(g->phi[0]);
+  a.fout = static_cast<T*>(g->f[dst]);
+  a.phiout = static_cast<T*>(g->phi[dst]);
+  a.rows = static_cast<const RowCoef<T>*>(g->rows);
+  a.nt = g->p.n_theta;
+  a.np = g->p.n_phi;
+  a.ntx = (a.np + TX - 1) / TX;
+  a.nty = (a.nt + TY - 1) / TY;
+  a.plane = (long long)a.nt * a.np;
+  a.has_y0 = stage != 1;
+  a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
+  a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
+  a.c = make_consts<T>(g->p);
+  const int nblk = a.ntx * a.nty;
+  hipLaunchKernelGGL(tlb_stage_kernel<T>, dim3(nblk), dim3(NT), 0, g->stream, a);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t step_n_t(tlb_grid* g, int64_t n) {
+  for (int64_t t = 0; t < n; ++t)
+    for (int st = 1; st <= 3; ++st) {
+      int32_t rc = launch_stage<T>(g, st);
+      if (rc != TLB_OK) return rc;
+    }
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t init_feq_t(tlb_grid* g, const void* n, const void* ut, const void* up) {
+  const long long plane = (long long)g->p.n_theta * g->p.n_phi;
+  const int blocks = (int)((plane + 255) / 256);
+  hipLaunchKernelGGL(tlb_init_feq_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
+                     static_cast<T*>(g->f[0]), static_cast<const T*>(n),
+                     static_cast<const T*>(ut), static_cast<const T*>(up), plane);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t moments_t(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu) {
+  const long long plane = (long long)g->p.n_theta * g->p.n_phi;
+  const int blocks = (int)((plane + 255) / 256);
+  hipLaunchKernelGGL(tlb_moments_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
+                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]),
+                     static_cast<T*>(n), static_cast<T*>(ut), static_cast<T*>(up),
+                     static_cast<T*>(phi), static_cast<T*>(mu),
+                     static_cast<const RowCoef<T>*>(g->rows), g->p.n_theta, g->p.n_phi,
+                     T(g->p.A), T(g->p.kappa));
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t reduce_t(tlb_grid* g) {
+  hipLaunchKernelGGL(tlb_reduce_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0,
+                     g->stream, static_cast<const T*>(g->f[0]),
+                     static_cast<const T*>(g->phi[0]), g->area, g->p.n_theta, g->p.n_phi,
+                     g->rows_per_block, g->partial);
+  TLB_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(tlb_reduce_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream,
+                     g->partial, g->red_blocks, g->partial + 3 * g->red_blocks);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+int32_t check_params(const tlb_params* p) {
+  if (!p) return fail(TLB_EINVAL, "params is NULL");
+  if (!(p->r > 0.0) || !std::isfinite(p->r)) return fail(TLB_EINVAL, "r must be > 0");
+  if (!(p->R > p->r) || !std::isfinite(p->R)) return fail(TLB_EINVAL, "R must exceed r");
+  if (p->n_theta < 1 || p->n_phi < 1) return fail(TLB_EINVAL, "grid sides must be >= 1");
+  if ((long long)p->n_theta * p->n_phi > (1LL << 31) / 16)
+    return fail(TLB_EINVAL, "grid too large for 32-bit in-plane offsets");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(TLB_EINVAL, "dt must be > 0");
+  if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(TLB_EINVAL, "tau must be > 0");
+  if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
+    return fail(TLB_EINVAL, "kappa must be >= 0");
+  if (!(p->M >= 0.0) || !std::isfinite(p->M)) return fail(TLB_EINVAL, "M must be >= 0");
+  if (!std::isfinite(p->A)) return fail(TLB_EINVAL, "A must be finite");
+  if (p->precision != 32 && p->precision != 64)
+    return fail(TLB_EINVAL, "precision must be 32 or 64");
+  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION)) return fail(TLB_EINVAL, "unknown flag");
+  return TLB_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* tlb_last_error(void) { return g_last_error.c_str(); }
+
+int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffers,
+                              void* hip_stream, tlb_grid** out) {
+  g_last_error.clear();
+  if (!out) return fail(TLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t rc = check_params(params);
+  if (rc != TLB_OK) return rc;
+  if (!buffers) return fail(TLB_EINVAL, "buffers is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!buffers->f[i] || !buffers->phi[i]) return fail(TLB_EINVAL, "a state buffer is NULL");
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j) {
+      const void* x = i < 3 ? buffers->f[i] : buffers->phi[i - 3];
+      const void* y = j < 3 ? buffers->f[j] : buffers->phi[j - 3];
+      if (x == y) return fail(TLB_EINVAL, "state buffers must be distinct");
+    }
+  tlb_grid* g = new (std::nothrow) tlb_grid{};
+  if (!g) return fail(TLB_ENOMEM, "host allocation failed");
+  g->p = *params;
+  for (int i = 0; i < 3; ++i) {
+    g->f[i] = buffers->f[i];
+    g->phi[i] = buffers->phi[i];
+  }
+  g->stream = static_cast<hipStream_t>(hip_stream);
+  g->elem = params->precision == 64 ? sizeof(double) : sizeof(float);
+  const int nt = params->n_theta;
+  g->rows_per_block = nt <= 512 ? 1 : (nt + 511) / 512;
+  g->red_blocks = (nt + g->rows_per_block - 1) / g->rows_per_block;
+
+  const size_t row_bytes =
+      params->precision == 64 ? sizeof(RowCoef<double>) : sizeof(RowCoef<float>);
+  void* host_rows = std::malloc(row_bytes * nt);
+  double* host_area = static_cast<double*>(std::malloc(sizeof(double) * nt));
+  auto cleanup = [&](int32_t code, const std::string& msg) {
+    std::free(host_rows);
+    std::free(host_area);
+    if (g->rows) (void)hipFree(g->rows);
+    if (g->area) (void)hipFree(g->area);
+    if (g->partial) (void)hipFree(g->partial);
+    delete g;
+    return fail(code, msg);
+  };
+  if (!host_rows || !host_area) return cleanup(TLB_ENOMEM, "host allocation failed");
+  if (params->precision == 64)
+    make_rows<double>(*params, static_cast<RowCoef<double>*>(host_rows), host_area);
+  else
+    make_rows<float>(*params, static_cast<RowCoef<float>*>(host_rows), host_area);
+
+  hipError_t e = hipMalloc(&g->rows, row_bytes * nt);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->area), sizeof(double) * nt);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&g->partial),
+                  sizeof(double) * (3 * g->red_blocks + 3));
+  if (e != hipSuccess)
+    return cleanup(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemcpyAsync(g->rows, host_rows, row_bytes * nt, hipMemcpyHostToDevice, g->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->area, host_area, sizeof(double) * nt, hipMemcpyHostToDevice,
+                       g->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return cleanup(TLB_EHIP, std::string("upload: ") + hipGetErrorString(e));
+  std::free(host_rows);
+  std::free(host_area);
+  *out = g;
+  return TLB_OK;
+}
+
+void tlb_destroy(tlb_grid* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  (void)hipFree(g->rows);
+  (void)hipFree(g->area);
+  (void)hipFree(g->partial);
+  delete g;
+}
+
+int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n,
+                      const void* ut, const void* up) {
+  g_last_error.clear();
+  if (!g || !phi) return fail(TLB_EINVAL, "grid or phi is NULL");
+  if (!f && (!n || !ut || !up)) return fail(TLB_EINVAL, "f is NULL and a moment field is NULL");
+  const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
+  TLB_HIP_CHECK(hipMemcpyAsync(g->phi[0], phi, plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  if (f) {
+    TLB_HIP_CHECK(
+        hipMemcpyAsync(g->f[0], f, 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+    return TLB_OK;
+  }
+  return g->p.precision == 64 ? init_feq_t<double>(g, n, ut, up)
+                              : init_feq_t<float>(g, n, ut, up);
+}
+
+int32_t tlb_step_n(tlb_grid* g, int64_t n_steps) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
+  return g->p.precision == 64 ? step_n_t<double>(g, n_steps) : step_n_t<float>(g, n_steps);
+}
+
+int32_t tlb_get_moments(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  return g->p.precision == 64 ? moments_t<double>(g, n, ut, up, phi, mu)
+                              : moments_t<float>(g, n, ut, up, phi, mu);
+}
+
+int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
+  if (f)
+    TLB_HIP_CHECK(
+        hipMemcpyAsync(f, g->f[0], 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  if (phi)
+    TLB_HIP_CHECK(
+        hipMemcpyAsync(phi, g->phi[0], plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  return TLB_OK;
+}
+
+int32_t tlb_invariants(tlb_grid* g, double out[3]) {
+  g_last_error.clear();
+  if (!g || !out) return fail(TLB_EINVAL, "grid or out is NULL");
+  int32_t rc = g->p.precision == 64 ? reduce_t<double>(g) : reduce_t<float>(g);
+  if (rc != TLB_OK) return rc;
+  TLB_HIP_CHECK(hipMemcpyAsync(out, g->partial + 3 * g->red_blocks, 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, g->stream));
+  TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (out[2] > 0) return fail(TLB_ENONFINITE, "non-finite values in the state");
+  return TLB_OK;
+}
+
+}  // extern "C"

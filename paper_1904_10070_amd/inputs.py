@@ -1,0 +1,165 @@
+"""Seeded synthetic inputs: parameter sets and initial fields for the torus workloads.
+
+This module holds no step arithmetic of the method.  It builds the initial order parameter
+and the moments (n, u) from which both the GPU library and the CPU oracle set their own
+equilibrium populations; both sides receive the very same host arrays.
+
+Initial conditions follow the paper:
+  * stripe: tanh profile with the Laplace-pressure offset phi_0 (section III A, eqs.
+    stripe_tanh and stripe_phi0);
+  * drop: tanh of the 3-D chord distance to the drop centre (section III D, eq. drop_init);
+  * spinodal: phi = mean + uniform noise in (-0.1, 0.1) (section IV, eq. phirand);
+  * populations at rest: f = f_eq(n0, u = 0) (section IV).
+
+Parameter sets: lengths in units of the minor radius r; k_B T = m = 1 so nu = tau.  The
+interface-width rule of the "interface about 3 cells" workloads is
+xi_0 = 3 h_max / (2 sqrt 2), h_max = max(r dtheta, 2 pi (R + r) / N_phi), kappa = A xi_0^2
+(xi_0 = sqrt(kappa / A), eq. xi_gamma).
+"""
+import math
+from dataclasses import dataclass, asdict, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class TorusParams:
+    r: float
+    R: float
+    n_theta: int
+    n_phi: int
+    A: float
+    kappa: float
+    M: float
+    tau: float
+    dt: float
+    flags: int = 0
+
+    def as_dict(self):
+        return asdict(self)
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+    @property
+    def xi0(self):
+        return math.sqrt(self.kappa / self.A)
+
+    @property
+    def gamma(self):
+        return math.sqrt(8.0 * self.kappa * self.A / 9.0)
+
+
+def xi0_three_cells(r, R, n_theta, n_phi):
+    h_max = max(r * 2 * math.pi / n_theta, 2 * math.pi * (R + r) / n_phi)
+    return 3.0 * h_max / (2.0 * math.sqrt(2.0))
+
+
+def params_three_cells(r, R, n_theta, n_phi, A, M, tau, dt, flags=0):
+    xi0 = xi0_three_cells(r, R, n_theta, n_phi)
+    return TorusParams(r, R, n_theta, n_phi, A, A * xi0 * xi0, M, tau, dt, flags)
+
+
+# -- the named workloads ------------------------------------------------------------------------
+
+def drop_workload():
+    """64 x 160 torus, r = 1, R = 2.5, one drop of radius 0.6 near theta = pi/2; 2000 steps."""
+    return params_three_cells(1.0, 2.5, 64, 160, A=0.5, M=0.1, tau=0.8, dt=5e-4)
+
+
+def stripe_workload(R=2.0, n_theta=256, n_phi=640):
+    """Stripe relaxation: r = 1, kappa = 5e-4, A = 0.5, nu = tau = M = 2.5e-3, dt = 5e-4."""
+    return TorusParams(1.0, R, n_theta, n_phi, 0.5, 5e-4, 2.5e-3, 2.5e-3, 5e-4)
+
+
+def spinodal_workload(tau=0.6, n_theta=512, n_phi=1280):
+    """Spinodal coarsening: r = 1, R = 2.5, M = 2.5e-3, tau 0.6 or 2.0, dt = 4e-4."""
+    return params_three_cells(1.0, 2.5, n_theta, n_phi, A=0.5, M=2.5e-3, tau=tau, dt=4e-4)
+
+
+def roofline_workload():
+    """The spinodal workload on a 2048 x 5120 grid (working set far above the 256 MB MALL)."""
+    p = spinodal_workload(0.6, 2048, 5120)
+    return p.with_(dt=1e-5)
+
+
+# -- fields ---------------------------------------------------------------------------------------
+
+def angles(n_theta, n_phi):
+    th = np.arange(n_theta) * (2 * np.pi / n_theta)
+    ph = np.arange(n_phi) * (2 * np.pi / n_phi)
+    return th, ph
+
+
+def rest_moments(n_theta, n_phi, n0=1.0):
+    """(n, u_theta, u_phi) of a fluid at rest with uniform density n0."""
+    shape = (n_theta, n_phi)
+    return np.full(shape, float(n0)), np.zeros(shape), np.zeros(shape)
+
+
+def periodic_distance(a, b):
+    """Smallest angular distance |a - b| on the circle, in [0, pi]."""
+    d = np.mod(a - b, 2 * np.pi)
+    return np.minimum(d, 2 * np.pi - d)
+
+
+def stripe_offset(xi0, R, a, theta_c, dtheta):
+    """Laplace-pressure offset phi_0 of eq. stripe_phi0."""
+    return (xi0 / (3 * R * math.sqrt(2.0)) * math.cos(theta_c) * math.sin(dtheta / 2) /
+            (1 + a * math.cos(theta_c) * math.cos(dtheta / 2)))
+
+
+def stripe_phi(p, theta_c, dtheta, offset=True, sign=1.0):
+    """Stripe of angular width dtheta centred on theta_c (eq. stripe_tanh), phi-independent.
+
+    sign = +1 gives the paper's convention (the stripe is the phi = -1 minority phase);
+    sign = -1 is its phi -> -phi image (a phi = +1 band).
+    """
+    th, _ = angles(p.n_theta, p.n_phi)
+    xi0 = p.xi0
+    phi0 = stripe_offset(xi0, p.R, p.r / p.R, theta_c, dtheta) if offset else 0.0
+    prof = phi0 + np.tanh(p.r / (xi0 * math.sqrt(2.0)) *
+                          (periodic_distance(th, theta_c) - dtheta / 2))
+    return sign * np.repeat(prof[:, None], p.n_phi, axis=1)
+
+
+def torus_xyz(r, R, th, ph):
+    """Embedding of eq. torus."""
+    rho = R + r * np.cos(th)
+    return rho * np.cos(ph), rho * np.sin(ph), r * np.sin(th)
+
+
+def drop_phi(p, theta0, phi0, R0, xi0=None):
+    """tanh((d - R0)/(xi0 sqrt 2)), d the 3-D chord distance to the centre (eq. drop_init)."""
+    xi0 = p.xi0 if xi0 is None else xi0
+    th, ph = angles(p.n_theta, p.n_phi)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    x, y, z = torus_xyz(p.r, p.R, T, P)
+    xc, yc, zc = torus_xyz(p.r, p.R, theta0, phi0)
+    d = np.sqrt((x - xc) ** 2 + (y - yc) ** 2 + (z - zc) ** 2)
+    return np.tanh((d - R0) / (xi0 * math.sqrt(2.0)))
+
+
+def drop_workload_phi(p, seed=1, R0=0.6):
+    """Drop of radius R0 centred at (pi/2, 0) with a seeded +/-1 % jitter of each period."""
+    rng = np.random.default_rng(seed)
+    u1, u2 = rng.uniform(-0.5, 0.5, size=2)
+    return drop_phi(p, 0.5 * np.pi + 0.02 * np.pi * u1, 0.02 * np.pi * u2, R0)
+
+
+def spinodal_phi(p, seed=7, mean=0.0, amp=0.1):
+    """phi = mean + i.i.d. uniform noise in (-amp, amp) (eq. phirand)."""
+    rng = np.random.default_rng(seed)
+    return mean + rng.uniform(-amp, amp, size=(p.n_theta, p.n_phi))
+
+
+def random_state(p, seed=0, amp_phi=0.5, amp_u=0.05, amp_n=0.05):
+    """A smooth-plus-noise moment state for parity tests away from any equilibrium."""
+    rng = np.random.default_rng(seed)
+    th, ph = angles(p.n_theta, p.n_phi)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    phi = amp_phi * np.sin(T + 0.3) * np.cos(2 * P) + 0.1 * rng.uniform(-1, 1, T.shape)
+    n = 1.0 + amp_n * rng.uniform(-1, 1, T.shape)
+    ut = amp_u * rng.uniform(-1, 1, T.shape)
+    up = amp_u * rng.uniform(-1, 1, T.shape)
+    return phi, n, ut, up
