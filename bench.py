@@ -1,0 +1,149 @@
+"""Throughput of the torus step on one MI355X: node-updates per second and HBM roofline.
+
+A step is one full time step of the method (three fused stage launches of the SSP-RK3
+integrator: moments, chemical potential, interface force, BGK, upwind advection, velocity-space
+force and connection terms, Cahn-Hilliard) over the whole grid, with the state resident in HBM.
+
+Headline workload: spinodal coarsening on a 512 x 1280 torus (r = 1, R = 2.5, tau = 0.6,
+M = 2.5e-3, phi ~ U[-0.1, 0.1] from seed 7, n = 1, u = 0), populations stored and stepped in
+FP32.  The same line also carries the FP64 rate on that workload and the FP32 rate on a
+2048 x 5120 grid whose working set (2.1 GB) is far larger than the 256 MB last-level cache.
+
+Roofline: the stage kernel is HBM-bound.  Algorithmic traffic per node and time step is 136
+values (stage 1 reads y^n and writes y1: 16 + 16 populations, 1 + 1 phi; stages 2 and 3 read
+y_s and y^n and write one copy: 32 + 16 populations and 2 + 1 phi each), i.e. 544 B in FP32 and
+1088 B in FP64.  `achieved` is those bytes per launch (one third of a step) over the average
+launch time, measured with HIP events on the stream the kernels run on.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALUES_PER_NODE_STEP = 136
+
+
+def algorithmic_bytes_per_node_step(precision):
+    return VALUES_PER_NODE_STEP * (4 if precision == 32 else 8)
+
+
+def time_steps(grid, steps, warmup):
+    """Average time per step (s) over `steps` steps after `warmup` untimed ones."""
+    import torch
+    grid.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(grid.stream):
+        start.record(grid.stream)
+        grid.step(steps)
+        stop.record(grid.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) * 1e-3 / steps
+
+
+def gpu_leg(p, precision, steps, warmup, seed=7):
+    from paper_1904_10070_amd import TorusGrid, inputs
+    g = TorusGrid(p, precision=precision)
+    phi = inputs.spinodal_phi(p, seed=seed)
+    g.set_state(phi, *inputs.rest_moments(p.n_theta, p.n_phi))
+    t_step = time_steps(g, steps, warmup)
+    mass, phisum, bad = g.invariants()
+    nodes = p.n_theta * p.n_phi
+    nups = nodes / t_step
+    bytes_launch = algorithmic_bytes_per_node_step(precision) * nodes / 3.0
+    achieved = bytes_launch / (t_step / 3.0) / 1e9
+    g.close()
+    return dict(nups=nups, t_step=t_step, achieved_gbs=achieved, nonfinite=bad,
+                bytes_per_launch=bytes_launch)
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """The FP64 oracle on the host cores: a bounded number of steps of the same workload."""
+    from oracle import ref
+    from paper_1904_10070_amd import inputs
+    g = ref.RefGrid(**p.as_dict())
+    g.set_state(inputs.spinodal_phi(p, seed=7), *inputs.rest_moments(p.n_theta, p.n_phi))
+    t0 = time.perf_counter()
+    g.step(1)
+    one = time.perf_counter() - t0
+    n_more = max(1, min(50, int(budget_s / max(one, 1e-6)) - 1))
+    t0 = time.perf_counter()
+    g.step(n_more)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=p.n_theta * p.n_phi * n_more / dt, unit="node-updates/s", cores=cores,
+                kind="oracle",
+                sample=f"FP64 oracle, {n_more} steps of the {p.n_theta}x{p.n_phi} spinodal "
+                       f"workload after 1 warm-up step ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the torus step is measured on a single MI355X "
+              "(multi-GPU sharding is designed but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_10070_amd import inputs, load_library
+    load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    p = inputs.spinodal_workload(0.6)
+    head = gpu_leg(p, 32, args.steps, args.warmup)
+    out = {
+        "metric": "node-updates/s & % HBM peak, FP32 vs FP64",
+        "value": head["nups"],
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["t_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded spinodal initial condition, eq. phirand)",
+        "config": {"workload": "spinodal coarsening torus 512x1280, r=1, R=2.5, tau=0.6, "
+                               "M=2.5e-3, dt=4e-4, FP32 populations",
+                   "n_theta": p.n_theta, "n_phi": p.n_phi, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "kernel": "tlb_stage_kernel<float>",
+                     "bytes_per_launch": head["bytes_per_launch"]},
+    }
+    if not args.no_extra:
+        steps64 = max(10, args.steps // 2)
+        d = gpu_leg(p, 64, steps64, args.warmup)
+        out["fp64"] = {"value": d["nups"], "unit": "node-updates/s", "ms_per_step": d["t_step"] * 1e3,
+                       "steps": steps64, "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
+                       "achieved_gbs": d["achieved_gbs"]}
+        pr = inputs.roofline_workload()
+        steps_r = max(10, args.steps // 20)
+        d = gpu_leg(pr, 32, steps_r, 5)
+        out["fp32_2048x5120"] = {"value": d["nups"], "unit": "node-updates/s",
+                                 "ms_per_step": d["t_step"] * 1e3, "steps": steps_r,
+                                 "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
+                                 "achieved_gbs": d["achieved_gbs"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,10 +100,12 @@ constexpr int HX = 3, HY = 3;    // population halo (UW5 needs 3 upwind, 2 downw
 constexpr int LX = TX + 2 * HX;  // 70
 constexpr int LY = TY + 2 * HY;  // 10
 constexpr int NT = TX * TY;      // 256 threads
-constexpr int FSLOTS = (LX * LY + NT - 1) / NT;  // 3 loads per thread per population
-constexpr int PX = TX + 4, PY = TY + 4;          // order-parameter tile with a 2-node halo
-constexpr int PSLOTS = (PX * PY + NT - 1) / NT;  // 3
-constexpr int NRING = 2 * TX + 2 * TY;           // cross-shaped ring of 1 node
+constexpr int PX = TX + 4, PY = TY + 4;  // order-parameter tile with a 2-node halo
+constexpr int NRING = 2 * TX + 2 * TY;   // cross-shaped ring of 1 node
+// Halo tiles are filled by asynchronous global->LDS copies (LDS DMA): every thread copies
+// TILE_SLOTS / NT elements, padded so that each wavefront issues the same number of copies.
+constexpr int TILE_SLOTS = 3 * NT;  // >= LX * LY = 700 and >= PX * PY = 544
+static_assert(LX * LY <= TILE_SLOTS && PX * PY <= TILE_SLOTS, "tile exceeds its DMA slots");
 static_assert(NRING <= NT, "ring nodes must fit one per thread");
 
 // UW5 flux difference (face_{+1/2} - face_{-1/2}) for a positive velocity, offsets -3..+2;
@@ -169,6 +171,61 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 __device__ __forceinline__ void pin_reg(float& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void pin_reg(double& x) { asm volatile("" : "+v"(x)); }
 
+// s_waitcnt immediate (gfx9 encoding): wait until at most `vm` vector-memory operations of this
+// wave are outstanding and all LDS operations are done; exp count not waited on.
+template <int VM>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt out of range");
+  __builtin_amdgcn_s_waitcnt((VM & 0xF) | (0x7 << 4) | (0x0 << 8) | (((VM >> 4) & 0x3) << 14));
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+// word 3 of a raw buffer resource descriptor on the gfx9 family (32-bit dword format)
+constexpr int BUF_DWORD3 = 0x00020000;
+
+// Dword copies of one halo tile of T elements: dword d = i * NT + tid (i < DW) of the tile
+// holds element d / DW_PER... precomputed as byte offsets within one plane.
+template <typename T>
+struct TileCopy {
+  static constexpr int DW = TILE_SLOTS * (int)sizeof(T) / 4 / NT;  // dword copies per thread
+  unsigned boff[DW];
+  // element index e of the tile -> (row, column) of a tile with `w` columns starting at
+  // (r0, c0) relative to the tile origin (q0, s0); wrap periodically unless `interior`.
+  __device__ __forceinline__ void init(int tid, int q0, int s0, int nt, int np, int w, int h,
+                                       int r0, int c0, bool interior) {
+#pragma unroll
+    for (int i = 0; i < DW; ++i) {
+      const int d = i * NT + tid;
+      const int e = d / (int)(sizeof(T) / 4);
+      const int half = d - e * (int)(sizeof(T) / 4);
+      unsigned off = 0;
+      if (e < w * h) {
+        const int yy = e / w, xx = e - yy * w;
+        int gq = q0 + yy + r0, gs = s0 + xx + c0;
+        if (!interior) {
+          gq = wrapi(gq, nt);
+          gs = wrapi(gs, np);
+        }
+        off = (unsigned)(gq * np + gs) * (unsigned)sizeof(T);
+      }
+      boff[i] = off + 4u * (unsigned)half;
+    }
+  }
+  // issue the copies of the plane at `base` (plane_bytes long) into `lds`, a TILE_SLOTS-element
+  // array: buffer loads with the plane in a resource descriptor (range-checked by the
+  // hardware) and a 32-bit lane offset, written by the load unit straight into LDS
+  __device__ __forceinline__ void issue(const T* base, unsigned plane_bytes, T* lds,
+                                        int wave) const {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, plane_bytes, BUF_DWORD3);
+#pragma unroll
+    for (int i = 0; i < DW; ++i) {
+      char* l = reinterpret_cast<char*>(lds) + 4 * (i * NT + wave * 64);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)l, 4, boff[i], 0, 0, 0);
+    }
+  }
+};
+
 // chemical potential (eq. mu) at local node (y, x) in [-1, TY] x [-1, TX] of the phi tile
 template <typename T>
 __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>& rc, T A,
@@ -180,49 +237,66 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
   return A * ph * (ph * ph - T(1)) - kappa * lap;
 }
 
+// population ring depth: copies of up to RING-1 populations are in flight while one is used
+template <typename T>
+struct Ring {
+  static constexpr int D = sizeof(T) == 4 ? 6 : 4;
+};
+
 template <typename T>
 __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
-  __shared__ T sF[2][LY * LX];
-  __shared__ T sPhi[PY * PX];
+  constexpr int D = Ring<T>::D;
+  constexpr int DW = TileCopy<T>::DW;
+  static_assert(D >= 2 && D <= 8, "ring depth");
+  // the ring slots are separate LDS objects, so that the compiler can see that reading one
+  // slot does not depend on the copies still in flight into the others
+  __shared__ T sF0[TILE_SLOTS], sF1[TILE_SLOTS], sF2[D > 2 ? TILE_SLOTS : 1],
+      sF3[D > 3 ? TILE_SLOTS : 1], sF4[D > 4 ? TILE_SLOTS : 1], sF5[D > 5 ? TILE_SLOTS : 1],
+      sF6[D > 6 ? TILE_SLOTS : 1], sF7[D > 7 ? TILE_SLOTS : 1];
+  auto slot = [&](auto sc) -> T* {
+    constexpr int S = decltype(sc)::value % D;
+    if constexpr (S == 0) return sF0;
+    else if constexpr (S == 1) return sF1;
+    else if constexpr (S == 2) return sF2;
+    else if constexpr (S == 3) return sF3;
+    else if constexpr (S == 4) return sF4;
+    else if constexpr (S == 5) return sF5;
+    else if constexpr (S == 6) return sF6;
+    else return sF7;
+  };
+  __shared__ T sPhi[TILE_SLOTS];
   __shared__ T sMu[(TY + 2) * (TX + 2)];
   __shared__ T sPt[(TY + 2) * TX];  // J u^theta phi on the tile and the rows above/below
   __shared__ T sPp[TY * (TX + 2)];  // u^phi phi on the tile and the columns left/right
 
   const int tid = threadIdx.x;
   const int lx = tid & (TX - 1);
-  const int ly = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform row
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ly = wave;  // wavefront-uniform row of the tile
   const int nt = a.nt, np = a.np;
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
   const int q0 = ty * TY, s0 = tx * TX;
   const int q = q0 + ly, s = s0 + lx;
   const bool active = (q < nt) && (s < np);
-  const int qw = wrapi(q, nt);
-  const RowCoef<T>& rc = a.rows[qw];
+  const int qw = __builtin_amdgcn_readfirstlane(q < nt ? q : wrapi(q, nt));
+  // this row's coefficients, read once (scalar loads: the row is wavefront-uniform) and kept
+  // in registers -- a reference would be re-read from memory after every barrier
+  const RowCoef<T> rc = a.rows[qw];
+  // no periodic wrap needed for any halo of this tile
+  const bool interior = q0 >= HY && q0 + TY + HY <= nt && s0 >= HX && s0 + TX + HX <= np;
 
-  // ---- order parameter tile with a 2-node halo (periodic wrap in both angles)
-#pragma unroll
-  for (int i = 0; i < PSLOTS; ++i) {
-    const int l = tid + i * NT;
-    if (l < PX * PY) {
-      const int yy = l / PX, xx = l - yy * PX;
-      const int gq = wrapi(q0 + yy - 2, nt), gs = wrapi(s0 + xx - 2, np);
-      sPhi[l] = a.phin[(long long)gq * np + gs];
-    }
-  }
-  // ---- population tile addresses (the same for every population), first prefetch
-  int off[FSLOTS];
-  bool ok[FSLOTS];
-#pragma unroll
-  for (int i = 0; i < FSLOTS; ++i) {
-    const int l = tid + i * NT;
-    ok[i] = l < LX * LY;
-    const int yy = l / LX, xx = l - yy * LX;
-    off[i] = ok[i] ? wrapi(q0 + yy - HY, nt) * np + wrapi(s0 + xx - HX, np) : 0;
-  }
-  T pre[FSLOTS];
-#pragma unroll
-  for (int i = 0; i < FSLOTS; ++i) pre[i] = ok[i] ? a.fin[off[i]] : T(0);
+  // ---- asynchronous halo copies: the order parameter, then populations 0..D-1 (one per slot);
+  //      from iteration k = 1 on, iteration k refills slot (k-1) mod D with population k+D-1
+  TileCopy<T> cp_phi, cp_f;
+  cp_phi.init(tid, q0, s0, nt, np, PX, PY, -2, -2, interior);
+  cp_f.init(tid, q0, s0, nt, np, LX, LY, -HY, -HX, interior);
+  const unsigned plane_bytes = (unsigned)(a.plane * (long long)sizeof(T));
+  cp_phi.issue(a.phin, plane_bytes, sPhi, wave);
+  static_for<0, D>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    cp_f.issue(a.fin + k * a.plane, plane_bytes, slot(ic<k>{}), wave);
+  });
 
   // ---- ring role: one cross-ring node per thread for tid < NRING
   int ry, rx;
@@ -234,13 +308,15 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   if (!ring) { ry = 0; rx = 0; }
   const RowCoef<T>& rrc = a.rows[wrapi(q0 + ry, nt)];
 
-  __syncthreads();
+  // order parameter copies done (the D population tiles may still be in flight)
+  wait_vm_lgkm0<DW * D>();
+  __builtin_amdgcn_s_barrier();
 
   // ---- chemical potential on the tile and the ring
   sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
   if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
 
-  // ---- stream the 16 populations through LDS
+  // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
   T rn = T(0), rut = T(0), rup = T(0);
   const int cN = (ly + HY) * LX + lx + HX;  // this node in the population tile
@@ -250,44 +326,48 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int i = k >> 2, j = k & 3;
-    T* buf = sF[k & 1];
-#pragma unroll
-    for (int sl = 0; sl < FSLOTS; ++sl)
-      if (ok[sl]) buf[tid + sl * NT] = pre[sl];
-    __syncthreads();
-    if constexpr (k < 15) {
-      const T* src = a.fin + (long long)(k + 1) * a.plane;
-#pragma unroll
-      for (int sl = 0; sl < FSLOTS; ++sl) pre[sl] = ok[sl] ? src[off[sl]] : T(0);
-    }
+    // populations issued before this point: D by the prologue, one more by each iteration
+    // 1..k-1 (capped at 16); wait until population k has landed
+    constexpr int issued_raw = k + D - 1 > D ? k + D - 1 : D;
+    constexpr int issued = issued_raw < 16 ? issued_raw : 16;
+    wait_vm_lgkm0<DW * (issued - k - 1)>();
+    __builtin_amdgcn_s_barrier();
+    // every wave is past population k-1: its ring slot can be refilled
+    if constexpr (k >= 1 && k + D - 1 < 16)
+      cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
+    const T* buf = slot(ic<k>{});
     f[k] = buf[cN];
     // phi direction: sum_o uw5(o) f_{s+o}, upwind side by the sign of v_j
-    T dph = T(0);
+    T dph;
     if constexpr (j >= 2) {
-      static_for<-3, 3>([&](auto oc) {
+      dph = T(uw5p(-3)) * buf[cN - 3];
+      static_for<-2, 3>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         dph += T(uw5p(o)) * buf[cN + o];
       });
     } else {
-      static_for<-2, 4>([&](auto oc) {
+      dph = T(uw5m(-2)) * buf[cN - 2];
+      static_for<-1, 4>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         dph += T(uw5m(o)) * buf[cN + o];
       });
     }
     // theta direction: sum_o uw5(o) J_{q+o} / (r J_q dtheta) f_{q+o}
-    T dth = T(0);
+    T dth;
     if constexpr (i >= 2) {
-      static_for<-3, 3>([&](auto oc) {
+      dth = rc.bth_p[0] * buf[cN - 3 * LX];
+      static_for<-2, 3>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         dth += rc.bth_p[o + 3] * buf[cN + o * LX];
       });
     } else {
-      static_for<-2, 4>([&](auto oc) {
+      dth = rc.bth_m[0] * buf[cN - 2 * LX];
+      static_for<-1, 4>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         dth += rc.bth_m[o + 2] * buf[cN + o * LX];
       });
     }
-    adv[k] = -(T(vel(i)) * dth + (T(vel(j)) * inv_Jdph) * dph);
+    adv[k] = T(-vel(i)) * dth + (T(-vel(j)) * inv_Jdph) * dph;
     if (ring) {
       const T fr = buf[cR];
       rn += fr;
@@ -653,8 +733,8 @@ int32_t check_params(const tlb_params* p) {
   if (!(p->r > 0.0) || !std::isfinite(p->r)) return fail(TLB_EINVAL, "r must be > 0");
   if (!(p->R > p->r) || !std::isfinite(p->R)) return fail(TLB_EINVAL, "R must exceed r");
   if (p->n_theta < 1 || p->n_phi < 1) return fail(TLB_EINVAL, "grid sides must be >= 1");
-  if ((long long)p->n_theta * p->n_phi > (1LL << 31) / 16)
-    return fail(TLB_EINVAL, "grid too large for 32-bit in-plane offsets");
+  if ((long long)p->n_theta * p->n_phi * (p->precision == 64 ? 8 : 4) > 0xFFFFFFFFLL)
+    return fail(TLB_EINVAL, "grid too large: one population plane must stay below 4 GiB");
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(TLB_EINVAL, "dt must be > 0");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(TLB_EINVAL, "tau must be > 0");
   if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
