@@ -122,6 +122,31 @@ def measured_laplace_pressure(n, phi, A, theta_c):
     return float(p[qi] - p[qo])
 
 
+def fit_damped_oscillation_window(t, dtheta, omega_guess, alpha_guess, t_min):
+    """Least squares of A cos(omega t + s) exp(-alpha t) + c over the samples with t >= t_min.
+
+    Amplitude, phase and offset are free; the early part of the record, where the initial
+    tanh profile relaxes to the torus equilibrium profile, is left out.  Returns
+    (omega, alpha).
+    """
+    from scipy.optimize import least_squares
+    t = np.asarray(t, float)
+    y = np.asarray(dtheta, float)
+    m = t >= t_min
+    tt, yy = t[m], y[m]
+
+    def res(x):
+        A, w, ph, al, c = x
+        return A * np.cos(w * tt + ph) * np.exp(-al * tt) + c - yy
+
+    best = None
+    for ph0 in np.linspace(0, 2 * np.pi, 8, endpoint=False):
+        s = least_squares(res, [np.abs(yy).max(), omega_guess, ph0, alpha_guess, 0.0])
+        if best is None or s.cost < best.cost:
+            best = s
+    return float(best.x[1]), float(best.x[3])
+
+
 def fit_damped_oscillation(t, dtheta, dtheta0):
     """Least squares of dtheta0 cos(omega t) exp(-alpha t) (eq. stripe_hydro_sol, phase 0)."""
     from scipy.optimize import least_squares
@@ -138,3 +163,16 @@ def fit_damped_oscillation(t, dtheta, dtheta0):
     w0 = math.pi / 2 / t[idx[0] + 1] if idx.size else 2 * math.pi / (t[-1] + 1e-30)
     sol = least_squares(res, x0=[w0, 1e-3], bounds=([0, -1], [np.inf, np.inf]))
     return float(sol.x[0]), float(sol.x[1])
+
+
+def minority_centroid_theta(phi, J, minority_sign=-1.0):
+    """theta of the area-weighted circular centroid of the minority phase (a drop's centre).
+
+    Weight (1 - minority_sign * ... ) / 2 clipped to [0, 1], i.e. the local fraction of the
+    minority phase, times the area element J (the common factor r dtheta dphi drops out)."""
+    phi = np.asarray(phi)
+    nt = phi.shape[0]
+    th = np.arange(nt) * 2 * math.pi / nt
+    wgt = np.clip((1 + minority_sign * phi) / 2, 0, 1) * np.asarray(J)[:, None]
+    z = (wgt * np.exp(1j * th)[:, None]).sum()
+    return math.atan2(z.imag, z.real) % (2 * math.pi)

@@ -1,0 +1,90 @@
+"""The C interface of libtlb.so, checked without a GPU: every function declared in
+include/tlb.h is exported, and argument validation (which happens before any HIP call)
+reports TLB_EINVAL with a message."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1904_10070_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tlb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlb_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load_library()
+
+
+def test_header_declares_the_interface():
+    names = declared_functions()
+    for n in ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments"):
+        assert n in names
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def params(**kw):
+    d = dict(r=1.0, R=2.5, n_theta=8, n_phi=16, A=0.5, kappa=1e-3, M=0.1, tau=0.5, dt=1e-3,
+             precision=64, flags=0)
+    d.update(kw)
+    return binding.Params(**d)
+
+
+@pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=1.0), dict(n_theta=0), dict(n_phi=-3),
+                                 dict(dt=0.0), dict(tau=0.0), dict(kappa=-1.0), dict(M=-0.1),
+                                 dict(precision=16), dict(flags=8), dict(A=float("nan")),
+                                 dict(n_theta=100000, n_phi=100000, precision=64)])
+def test_create_rejects_bad_parameters(lib, bad):
+    p = params(**bad)
+    b = binding.Buffers()
+    for i in range(3):
+        b.f[i] = 0x1000 * (i + 1)
+        b.phi[i] = 0x1000 * (i + 4)
+    h = ctypes.c_void_p()
+    rc = lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(h))
+    assert rc == binding.TLB_EINVAL
+    assert h.value is None
+    assert lib.tlb_last_error()
+
+
+def test_create_rejects_missing_or_aliased_buffers(lib):
+    p = params()
+    h = ctypes.c_void_p()
+    assert lib.tlb_create_torus_grid(ctypes.byref(p), None, None, ctypes.byref(h)) == binding.TLB_EINVAL
+    b = binding.Buffers()
+    for i in range(3):
+        b.f[i] = 0x1000
+        b.phi[i] = 0x2000 * (i + 1)
+    rc = lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(h))
+    assert rc == binding.TLB_EINVAL and b"distinct" in lib.tlb_last_error()
+
+
+def test_null_handles_rejected(lib):
+    assert lib.tlb_step_n(None, 1) == binding.TLB_EINVAL
+    assert lib.tlb_set_state(None, None, None, None, None, None) == binding.TLB_EINVAL
+    assert lib.tlb_get_moments(None, None, None, None, None, None) == binding.TLB_EINVAL
+    assert lib.tlb_get_state(None, None, None) == binding.TLB_EINVAL
+    out = (ctypes.c_double * 3)()
+    assert lib.tlb_invariants(None, out) == binding.TLB_EINVAL
+    lib.tlb_destroy(None)
+
+
+def test_binding_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_1904_10070_amd import TorusGrid, inputs
+    with pytest.raises(RuntimeError):
+        TorusGrid(inputs.drop_workload())
