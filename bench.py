@@ -65,6 +65,40 @@ def gpu_leg(p, precision, steps, warmup, seed=7):
                 bytes_per_launch=bytes_launch)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of the stage kernel from the committed counter summary
+    (profiles/stage_kernel_traffic.json), or None if the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+    src = os.path.join(ROOT, "paper_1904_10070_amd", "csrc", "tlb.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("traffic_bytes_per_launch", {}).get(key)
+
+
+def copy_bandwidth(mib=1024, reps=20):
+    """Read+write bandwidth of a plain device-to-device copy (torch), for context: the
+    practical ceiling of a streaming kernel on this GPU, next to the 8 TB/s nominal peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    return 8.0 * n * reps / (start.elapsed_time(stop) * 1e-3) / 1e9
+
+
 def cpu_baseline(p, budget_s=15.0):
     """The FP64 oracle on the host cores: a bounded number of steps of the same workload."""
     from oracle import ref
@@ -92,6 +126,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
+    ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64"],
+                    help="time a single workload/precision (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, metavar="MIB",
+                    help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the torus step is measured on a single MI355X "
@@ -102,6 +141,30 @@ def main():
     from paper_1904_10070_amd import inputs, load_library
     load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 20
+        print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": 4 * n,
+                          "bytes_written": 4 * n, "gbs_read_plus_write": 8 * n / dt / 1e9}))
+        return
+    if args.only:
+        wl, prec = args.only[:-2], int(args.only[-2:])
+        p = inputs.spinodal_workload(0.6) if wl == "spinodal" else inputs.roofline_workload()
+        d = gpu_leg(p, prec, args.steps, args.warmup)
+        print(json.dumps({"workload": f"{wl} {p.n_theta}x{p.n_phi}", "precision": prec,
+                          "value": d["nups"], "unit": "node-updates/s",
+                          "ms_per_step": d["t_step"] * 1e3, "achieved_gbs": d["achieved_gbs"],
+                          "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
+                          "bytes_per_launch": d["bytes_per_launch"], "steps": args.steps}))
+        return
 
     p = inputs.spinodal_workload(0.6)
     head = gpu_leg(p, 32, args.steps, args.warmup)
@@ -123,9 +186,10 @@ def main():
                    "n_theta": p.n_theta, "n_phi": p.n_phi, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": measured_traffic("spinodal512x1280_fp32"),
                      "kernel": "tlb_stage_kernel<float>",
-                     "bytes_per_launch": head["bytes_per_launch"]},
+                     "bytes_per_launch": head["bytes_per_launch"],
+                     "copy_gbs": copy_bandwidth()},
     }
     if not args.no_extra:
         steps64 = max(10, args.steps // 2)

@@ -46,11 +46,14 @@ class Buffers(ctypes.Structure):
 _LIB = None
 
 
-def load_library(path=LIB_PATH):
-    """Load libtlb.so and declare its signatures; raises if it has not been built."""
+def load_library(path=None):
+    """Load libtlb.so and declare its signatures; raises if it has not been built.
+
+    TLB_LIBRARY in the environment selects another build of the same source (tuning runs)."""
     global _LIB
     if _LIB is not None:
         return _LIB
+    path = path or os.environ.get("TLB_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it first (python -m paper_1904_10070_amd.build)")
     lib = ctypes.CDLL(path)

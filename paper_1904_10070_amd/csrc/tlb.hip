@@ -95,17 +95,20 @@ __host__ __device__ __forceinline__ void static_for(F&& fn) {
 // ------------------------------------------------------------------------------------------
 // tile geometry of the stage kernel
 constexpr int TX = 64;           // nodes along phi per tile = wavefront width
-constexpr int TY = 4;            // nodes along theta per tile = wavefronts per block
-constexpr int HX = 3, HY = 3;    // population halo (UW5 needs 3 upwind, 2 downwind)
-constexpr int LX = TX + 2 * HX;  // 70
-constexpr int LY = TY + 2 * HY;  // 10
+#ifndef TLB_TY
+#define TLB_TY 8
+#endif
+constexpr int TY = TLB_TY;       // nodes along theta per tile = wavefronts per block
+constexpr int HY = 3;            // population halo rows (UW5 needs 3 upwind, 2 downwind)
 constexpr int NT = TX * TY;      // 256 threads
-constexpr int PX = TX + 4, PY = TY + 4;  // order-parameter tile with a 2-node halo
-constexpr int NRING = 2 * TX + 2 * TY;   // cross-shaped ring of 1 node
-// Halo tiles are filled by asynchronous global->LDS copies (LDS DMA): every thread copies
-// TILE_SLOTS / NT elements, padded so that each wavefront issues the same number of copies.
-constexpr int TILE_SLOTS = 3 * NT;  // >= LX * LY = 700 and >= PX * PY = 544
-static_assert(LX * LY <= TILE_SLOTS && PX * PY <= TILE_SLOTS, "tile exceeds its DMA slots");
+constexpr int NWAVE = NT / 64;
+// LDS tiles hold rows of 72 elements: columns s0-4 .. s0+67, a 16-byte aligned window that
+// contains the 3-node phi halo of the populations and the 2-node halo of the order parameter.
+constexpr int LXT = TX + 8;
+constexpr int CX = 4;            // LDS column of the tile's first node
+constexpr int LY = TY + 2 * HY;  // population tile rows q0-3 .. q0+TY+2
+constexpr int PY = TY + 4;       // order-parameter tile rows q0-2 .. q0+TY+1
+constexpr int NRING = 2 * TX + 2 * TY;  // cross-shaped ring of 1 node
 static_assert(NRING <= NT, "ring nodes must fit one per thread");
 
 // UW5 flux difference (face_{+1/2} - face_{-1/2}) for a positive velocity, offsets -3..+2;
@@ -159,11 +162,27 @@ __device__ __forceinline__ int wrapi(int x, int n) {
 }
 
 // Block -> tile mapping: consecutive hardware blocks go round-robin over the 8 XCDs; give
-// XCD x the contiguous tile range [start_x, start_x + count_x) in row-major tile order.
+// XCD x the contiguous tile range [start_x, start_x + count_x) of a banded tile order (see
+// band_tile), so that the blocks resident on one XCD at a time form a compact patch whose
+// halo rows and halo cache lines are shared through that XCD's L2.
 __host__ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   const int xcd = b & 7, local = b >> 3;
   const int full = nblk >> 3, rem = nblk & 7;
   return xcd < rem ? xcd * (full + 1) + local : rem * (full + 1) + (xcd - rem) * full + local;
+}
+
+// Banded tile order: the tile columns are cut into bands of BAND columns (the last band may be
+// narrower); bands follow each other, and inside a band the tiles go row by row.
+#ifndef TLB_BAND
+#define TLB_BAND 8
+#endif
+constexpr int BAND = TLB_BAND;
+__host__ __device__ __forceinline__ void band_tile(int t, int ntx, int nty, int& tx, int& ty) {
+  const int band = t / (BAND * nty);
+  const int width = min(BAND, ntx - band * BAND);
+  const int local = t - band * BAND * nty;
+  ty = local / width;
+  tx = band * BAND + (local - ty * width);
 }
 
 // Empty register-to-register asm: the value must exist at this point of the program, so its
@@ -183,45 +202,74 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // word 3 of a raw buffer resource descriptor on the gfx9 family (32-bit dword format)
 constexpr int BUF_DWORD3 = 0x00020000;
 
-// Dword copies of one halo tile of T elements: dword d = i * NT + tid (i < DW) of the tile
-// holds element d / DW_PER... precomputed as byte offsets within one plane.
-template <typename T>
+// Asynchronous copy (LDS DMA) of one halo tile: ROWS rows of LXT elements of T, starting at
+// row q0 + R0 and column s0 - CX of a plane, stored row-major in LDS.  The copy unit is a
+// 16-byte chunk (VEC, possible when the row length n_phi keeps every chunk aligned and inside
+// one period) or a 4-byte word.  Copy instruction i of wave w moves the contiguous units
+// [i NT + w c_i, i NT + (w+1) c_i) with c_i = ceil(units of instruction i / waves), lanes past
+// the tile masked off; every wave thus issues every instruction, so all waves count the same
+// number of outstanding copies per tile (the waits below rely on it).
+template <typename T, bool VEC, int ROWS, int R0>
 struct TileCopy {
-  static constexpr int DW = TILE_SLOTS * (int)sizeof(T) / 4 / NT;  // dword copies per thread
-  unsigned boff[DW];
-  // element index e of the tile -> (row, column) of a tile with `w` columns starting at
-  // (r0, c0) relative to the tile origin (q0, s0); wrap periodically unless `interior`.
-  __device__ __forceinline__ void init(int tid, int q0, int s0, int nt, int np, int w, int h,
-                                       int r0, int c0, bool interior) {
+  static constexpr int UNIT = VEC ? 16 : 4;
+  static constexpr int ROW_UNITS = LXT * (int)sizeof(T) / UNIT;
+  static constexpr int UNITS = ROWS * ROW_UNITS;
+  static constexpr int INSTR = (UNITS + NT - 1) / NT;  // copy instructions per wave per tile
+  __host__ __device__ static constexpr int chunk(int i) {
+    const int v = UNITS - i * NT < NT ? UNITS - i * NT : NT;
+    return (v + NWAVE - 1) / NWAVE;
+  }
+  __host__ __device__ static constexpr bool every_wave_copies() {
+    for (int i = 0; i < INSTR; ++i) {
+      const int v = UNITS - i * NT < NT ? UNITS - i * NT : NT;
+      if (chunk(i) > 64 || (NWAVE - 1) * chunk(i) >= v) return false;
+    }
+    return true;
+  }
+  static_assert(every_wave_copies(), "a wave would issue no copy for some instruction");
+  static_assert((LXT * (int)sizeof(T)) % UNIT == 0, "row is not a whole number of units");
+
+  unsigned voff[INSTR];
+  bool valid[INSTR];
+
+  __device__ __forceinline__ void init(int lane, int wave, int q0, int s0, int nt, int np,
+                                       bool interior) {
 #pragma unroll
-    for (int i = 0; i < DW; ++i) {
-      const int d = i * NT + tid;
-      const int e = d / (int)(sizeof(T) / 4);
-      const int half = d - e * (int)(sizeof(T) / 4);
+    for (int i = 0; i < INSTR; ++i) {
+      const int u = i * NT + wave * chunk(i) + lane;
+      valid[i] = lane < chunk(i) && u < UNITS;
       unsigned off = 0;
-      if (e < w * h) {
-        const int yy = e / w, xx = e - yy * w;
-        int gq = q0 + yy + r0, gs = s0 + xx + c0;
+      if (valid[i]) {
+        const int row = u / ROW_UNITS, uc = u - row * ROW_UNITS;
+        int col, byte_in_elem = 0;
+        if constexpr (VEC) {
+          col = uc * (UNIT / (int)sizeof(T));
+        } else {
+          col = uc / ((int)sizeof(T) / 4);
+          byte_in_elem = 4 * (uc - col * ((int)sizeof(T) / 4));
+        }
+        int gq = q0 + R0 + row, gs = s0 - CX + col;
         if (!interior) {
           gq = wrapi(gq, nt);
           gs = wrapi(gs, np);
         }
-        off = (unsigned)(gq * np + gs) * (unsigned)sizeof(T);
+        off = (unsigned)(gq * np + gs) * (unsigned)sizeof(T) + (unsigned)byte_in_elem;
       }
-      boff[i] = off + 4u * (unsigned)half;
+      voff[i] = off;
     }
   }
-  // issue the copies of the plane at `base` (plane_bytes long) into `lds`, a TILE_SLOTS-element
-  // array: buffer loads with the plane in a resource descriptor (range-checked by the
-  // hardware) and a 32-bit lane offset, written by the load unit straight into LDS
+  // copy from the plane at `base` (plane_bytes long) into the LDS tile `lds`: buffer loads
+  // with the plane in a resource descriptor (range-checked by the hardware), written by the
+  // load unit straight into LDS
   __device__ __forceinline__ void issue(const T* base, unsigned plane_bytes, T* lds,
                                         int wave) const {
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, plane_bytes, BUF_DWORD3);
 #pragma unroll
-    for (int i = 0; i < DW; ++i) {
-      char* l = reinterpret_cast<char*>(lds) + 4 * (i * NT + wave * 64);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)l, 4, boff[i], 0, 0, 0);
+    for (int i = 0; i < INSTR; ++i) {
+      char* l = reinterpret_cast<char*>(lds) + UNIT * (i * NT + wave * chunk(i));
+      if (valid[i])
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)l, UNIT, voff[i], 0, 0, 0);
     }
   }
 };
@@ -230,23 +278,32 @@ struct TileCopy {
 template <typename T>
 __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>& rc, T A,
                                    T kappa) {
-  const int c = (y + 2) * PX + (x + 2);
+  const int c = (y + 2) * LXT + (x + CX);
   const T ph = sPhi[c];
-  const T lap = rc.lap_n * (sPhi[c + PX] - ph) - rc.lap_s * (ph - sPhi[c - PX]) +
+  const T lap = rc.lap_n * (sPhi[c + LXT] - ph) - rc.lap_s * (ph - sPhi[c - LXT]) +
                 rc.lap_p * (sPhi[c + 1] - T(2) * ph + sPhi[c - 1]);
   return A * ph * (ph * ph - T(1)) - kappa * lap;
 }
 
 // population ring depth: copies of up to RING-1 populations are in flight while one is used
+#ifndef TLB_RING32
+#define TLB_RING32 4
+#endif
+#ifndef TLB_RING64
+#define TLB_RING64 4
+#endif
 template <typename T>
 struct Ring {
-  static constexpr int D = sizeof(T) == 4 ? 6 : 4;
+  static constexpr int D = sizeof(T) == 4 ? TLB_RING32 : TLB_RING64;
 };
 
-template <typename T>
+template <typename T, bool VEC>
 __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   constexpr int D = Ring<T>::D;
-  constexpr int DW = TileCopy<T>::DW;
+  using CopyF = TileCopy<T, VEC, LY, -HY>;
+  using CopyPhi = TileCopy<T, VEC, PY, -2>;
+  constexpr int DW = CopyF::INSTR;
+  constexpr int TILE_SLOTS = LY * LXT;
   static_assert(D >= 2 && D <= 8, "ring depth");
   // the ring slots are separate LDS objects, so that the compiler can see that reading one
   // slot does not depend on the copies still in flight into the others
@@ -264,7 +321,7 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
     else if constexpr (S == 6) return sF6;
     else return sF7;
   };
-  __shared__ T sPhi[TILE_SLOTS];
+  __shared__ T sPhi[PY * LXT];
   __shared__ T sMu[(TY + 2) * (TX + 2)];
   __shared__ T sPt[(TY + 2) * TX];  // J u^theta phi on the tile and the rows above/below
   __shared__ T sPp[TY * (TX + 2)];  // u^phi phi on the tile and the columns left/right
@@ -275,7 +332,8 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   const int ly = wave;  // wavefront-uniform row of the tile
   const int nt = a.nt, np = a.np;
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
-  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
+  int tx, ty;
+  band_tile(tile, a.ntx, a.nty, tx, ty);
   const int q0 = ty * TY, s0 = tx * TX;
   const int q = q0 + ly, s = s0 + lx;
   const bool active = (q < nt) && (s < np);
@@ -284,13 +342,14 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   // in registers -- a reference would be re-read from memory after every barrier
   const RowCoef<T> rc = a.rows[qw];
   // no periodic wrap needed for any halo of this tile
-  const bool interior = q0 >= HY && q0 + TY + HY <= nt && s0 >= HX && s0 + TX + HX <= np;
+  const bool interior = q0 >= HY && q0 + TY + HY <= nt && s0 >= CX && s0 + LXT - CX <= np;
 
   // ---- asynchronous halo copies: the order parameter, then populations 0..D-1 (one per slot);
   //      from iteration k = 1 on, iteration k refills slot (k-1) mod D with population k+D-1
-  TileCopy<T> cp_phi, cp_f;
-  cp_phi.init(tid, q0, s0, nt, np, PX, PY, -2, -2, interior);
-  cp_f.init(tid, q0, s0, nt, np, LX, LY, -HY, -HX, interior);
+  CopyPhi cp_phi;
+  CopyF cp_f;
+  cp_phi.init(lx, wave, q0, s0, nt, np, interior);
+  cp_f.init(lx, wave, q0, s0, nt, np, interior);
   const unsigned plane_bytes = (unsigned)(a.plane * (long long)sizeof(T));
   cp_phi.issue(a.phin, plane_bytes, sPhi, wave);
   static_for<0, D>([&](auto kc) {
@@ -309,6 +368,7 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   const RowCoef<T>& rrc = a.rows[wrapi(q0 + ry, nt)];
 
   // order parameter copies done (the D population tiles may still be in flight)
+  static_assert(CopyPhi::INSTR + DW * D < 64, "outstanding copies exceed the vmcnt range");
   wait_vm_lgkm0<DW * D>();
   __builtin_amdgcn_s_barrier();
 
@@ -319,8 +379,8 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
   T rn = T(0), rut = T(0), rup = T(0);
-  const int cN = (ly + HY) * LX + lx + HX;  // this node in the population tile
-  const int cR = (ry + HY) * LX + rx + HX;  // the ring node
+  const int cN = (ly + HY) * LXT + lx + CX;  // this node in the population tile
+  const int cR = (ry + HY) * LXT + rx + CX;  // the ring node
   const T inv_Jdph = rc.inv_Jdph;
 
   static_for<0, 16>([&](auto kc) {
@@ -355,16 +415,16 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
     // theta direction: sum_o uw5(o) J_{q+o} / (r J_q dtheta) f_{q+o}
     T dth;
     if constexpr (i >= 2) {
-      dth = rc.bth_p[0] * buf[cN - 3 * LX];
+      dth = rc.bth_p[0] * buf[cN - 3 * LXT];
       static_for<-2, 3>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
-        dth += rc.bth_p[o + 3] * buf[cN + o * LX];
+        dth += rc.bth_p[o + 3] * buf[cN + o * LXT];
       });
     } else {
-      dth = rc.bth_m[0] * buf[cN - 2 * LX];
+      dth = rc.bth_m[0] * buf[cN - 2 * LXT];
       static_for<-1, 4>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
-        dth += rc.bth_m[o + 2] * buf[cN + o * LX];
+        dth += rc.bth_m[o + 2] * buf[cN + o * LXT];
       });
     }
     adv[k] = T(-vel(i)) * dth + (T(-vel(j)) * inv_Jdph) * dph;
@@ -395,11 +455,11 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   });
   const T inv_n = T(1) / n;
   const T ut = nut * inv_n, up = nup * inv_n;
-  const T phc = sPhi[(ly + 2) * PX + lx + 2];
+  const T phc = sPhi[(ly + 2) * LXT + lx + CX];
   sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
   sPp[ly * (TX + 2) + lx + 1] = up * phc;
   if (ring) {
-    const T phr = sPhi[(ry + 2) * PX + rx + 2];
+    const T phr = sPhi[(ry + 2) * LXT + rx + CX];
     const T inv_rn = T(1) / rn;
     if (ry < 0 || ry >= TY) sPt[(ry + 1) * TX + rx] = rrc.J * (rut * inv_rn) * phr;
     else sPp[ry * (TX + 2) + rx + 1] = (rup * inv_rn) * phr;
@@ -675,7 +735,10 @@ int32_t launch_stage(tlb_grid* g, int stage) {
   a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
   a.c = make_consts<T>(g->p);
   const int nblk = a.ntx * a.nty;
-  hipLaunchKernelGGL(tlb_stage_kernel<T>, dim3(nblk), dim3(NT), 0, g->stream, a);
+  // 16-byte copies need every 16-byte chunk of a row inside one period of phi
+  const bool vec = a.np % (16 / (int)sizeof(T)) == 0;
+  if (vec) hipLaunchKernelGGL((tlb_stage_kernel<T, true>), dim3(nblk), dim3(NT), 0, g->stream, a);
+  else hipLaunchKernelGGL((tlb_stage_kernel<T, false>), dim3(nblk), dim3(NT), 0, g->stream, a);
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
