@@ -49,10 +49,10 @@ def time_steps(grid, steps, warmup):
     return start.elapsed_time(stop) * 1e-3 / steps
 
 
-def gpu_leg(p, precision, steps, warmup, seed=7):
+def gpu_leg(p, precision, steps, warmup, seed=7, phi=None):
     from paper_1904_10070_amd import TorusGrid, inputs
     g = TorusGrid(p, precision=precision)
-    phi = inputs.spinodal_phi(p, seed=seed)
+    phi = inputs.spinodal_phi(p, seed=seed) if phi is None else phi
     g.set_state(phi, *inputs.rest_moments(p.n_theta, p.n_phi))
     t_step = time_steps(g, steps, warmup)
     mass, phisum, bad = g.invariants()
@@ -204,6 +204,11 @@ def main():
                                  "ms_per_step": d["t_step"] * 1e3, "steps": steps_r,
                                  "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
                                  "achieved_gbs": d["achieved_gbs"]}
+        # the small drop workload (64 x 160, FP64): launch-bound, stepped through the graph
+        pd = inputs.drop_workload()
+        d = gpu_leg(pd, 64, 2000, args.warmup, phi=inputs.drop_workload_phi(pd, seed=1))
+        out["drop64x160_fp64"] = {"value": d["nups"], "unit": "node-updates/s",
+                                  "ms_per_step": d["t_step"] * 1e3, "steps": 2000}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -18,7 +18,7 @@
  *
  * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
  * buffers); they must outlive the grid handle.  The library owns only its per-row geometry
- * table and a small reduction workspace, both freed by tlb_destroy.
+ * table, a small reduction workspace and the step graph, all freed by tlb_destroy.
  *
  * Streams.  All work is enqueued on the HIP stream given at creation (NULL = the default
  * stream), in call order, asynchronously with respect to the host.  Only tlb_invariants
@@ -46,6 +46,8 @@ extern "C" {
 #define TLB_FLAT 1u            /* flat limit: J = R and G = 0 (a doubly periodic plane with   *
                                 * spacings R dphi and r dtheta)                              */
 #define TLB_CH_NO_ADVECTION 2u /* drop -div(u phi) from the Cahn-Hilliard equation          */
+#define TLB_NO_GRAPH 4u        /* tlb_step_n launches every kernel itself instead of replaying *
+                                * a prebuilt graph of 32 time steps (same results, bit-exact) */
 
 /* Physical and numerical parameters, in the paper's units (k_B T = m = 1, so the kinematic
  * viscosity is nu = tau, eq. nu).
@@ -56,7 +58,7 @@ extern "C" {
  *   tau         BGK relaxation time (> 0)
  *   dt          time step of the three-stage SSP Runge-Kutta integrator (> 0)
  *   precision   32 or 64: element type T of every device buffer of this grid
- *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION                                              */
+ *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH                               */
 typedef struct tlb_params {
   double r, R;
   int32_t n_theta, n_phi;
@@ -97,8 +99,10 @@ int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void
  * f_eq (eq. feq); finite-difference advection along the vielbein frame with the metric
  * factors r and J (eq. boltz_tor); velocity-space force and connection terms through K^H
  * (section II C); Cahn-Hilliard right-hand side -div(u phi) + M Delta_S mu (eq. CH) --
- * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous.
- * Errors: TLB_EINVAL, TLB_EHIP (launch failure).                                           */
+ * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous.  Runs of 32 steps
+ * are replayed from a graph of kernel nodes built on first use (unless TLB_NO_GRAPH); the
+ * graph keeps the buffer pointers given at creation.
+ * Errors: TLB_EINVAL, TLB_EHIP (launch or graph failure).                                  */
 int32_t tlb_step_n(tlb_grid* grid, int64_t n_steps);
 
 /* Moments of the current state into caller buffers (any may be NULL): density n = sum f,

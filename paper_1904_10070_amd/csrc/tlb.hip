@@ -709,12 +709,14 @@ struct tlb_grid {
   double* partial;  // [3 * red_blocks + 3]
   int red_blocks, rows_per_block;
   size_t elem;
+  hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
+  bool chunk_tried;
 };
 
 namespace {
 
 template <typename T>
-int32_t launch_stage(tlb_grid* g, int stage) {
+StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   StageArgs<T> a{};
   const int src = stage == 1 ? 0 : stage - 1;  // stage 1 reads y^n, 2 reads y1, 3 reads y2
   const int dst = stage == 3 ? 0 : stage;      // stage 3 writes y^{n+1} over y^n
@@ -734,18 +736,80 @@ int32_t launch_stage(tlb_grid* g, int stage) {
   a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
   a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
   a.c = make_consts<T>(g->p);
-  const int nblk = a.ntx * a.nty;
-  // 16-byte copies need every 16-byte chunk of a row inside one period of phi
-  const bool vec = a.np % (16 / (int)sizeof(T)) == 0;
-  if (vec) hipLaunchKernelGGL((tlb_stage_kernel<T, true>), dim3(nblk), dim3(NT), 0, g->stream, a);
-  else hipLaunchKernelGGL((tlb_stage_kernel<T, false>), dim3(nblk), dim3(NT), 0, g->stream, a);
-  TLB_HIP_CHECK(hipGetLastError());
+  return a;
+}
+
+// the stage kernel variant for this grid: 16-byte copies need every 16-byte chunk of a row
+// inside one period of phi
+template <typename T>
+const void* stage_fn(const tlb_grid* g) {
+  const bool vec = g->p.n_phi % (16 / (int)sizeof(T)) == 0;
+  return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true>)
+             : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false>);
+}
+
+int stage_blocks(const tlb_grid* g) {
+  return ((g->p.n_phi + TX - 1) / TX) * ((g->p.n_theta + TY - 1) / TY);
+}
+
+template <typename T>
+int32_t launch_stage(tlb_grid* g, int stage) {
+  StageArgs<T> a = stage_args<T>(g, stage);
+  void* params[] = {&a};
+  TLB_HIP_CHECK(hipLaunchKernel(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(NT), params, 0,
+                                g->stream));
+  return TLB_OK;
+}
+
+// A chain of GRAPH_CHUNK time steps (3 GRAPH_CHUNK kernel nodes, each depending on the one
+// before) built explicitly -- no stream capture, so the caller's stream may be the legacy
+// default stream -- and replayed with one launch.  Kernel nodes only.
+constexpr int GRAPH_CHUNK = 32;
+
+template <typename T>
+int32_t build_chunk_graph(tlb_grid* g) {
+  hipGraph_t graph;
+  TLB_HIP_CHECK(hipGraphCreate(&graph, 0));
+  StageArgs<T> args[3] = {stage_args<T>(g, 1), stage_args<T>(g, 2), stage_args<T>(g, 3)};
+  hipGraphNode_t prev = nullptr;
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < GRAPH_CHUNK && e == hipSuccess; ++t)
+    for (int st = 0; st < 3 && e == hipSuccess; ++st) {
+      void* params[] = {&args[st]};
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(stage_fn<T>(g));
+      kp.gridDim = dim3(stage_blocks(g));
+      kp.blockDim = dim3(NT);
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = params;
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      prev = node;
+    }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->chunk_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g->chunk_exec = nullptr;
+    return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
+  }
   return TLB_OK;
 }
 
 template <typename T>
 int32_t step_n_t(tlb_grid* g, int64_t n) {
-  for (int64_t t = 0; t < n; ++t)
+  const bool use_graph = !(g->p.flags & TLB_NO_GRAPH) && n >= GRAPH_CHUNK;
+  if (use_graph && !g->chunk_tried) {
+    g->chunk_tried = true;
+    int32_t rc = build_chunk_graph<T>(g);
+    if (rc != TLB_OK) return rc;
+  }
+  int64_t done = 0;
+  if (use_graph && g->chunk_exec) {
+    for (; done + GRAPH_CHUNK <= n; done += GRAPH_CHUNK)
+      TLB_HIP_CHECK(hipGraphLaunch(g->chunk_exec, g->stream));
+  }
+  for (; done < n; ++done)
     for (int st = 1; st <= 3; ++st) {
       int32_t rc = launch_stage<T>(g, st);
       if (rc != TLB_OK) return rc;
@@ -806,7 +870,8 @@ int32_t check_params(const tlb_params* p) {
   if (!std::isfinite(p->A)) return fail(TLB_EINVAL, "A must be finite");
   if (p->precision != 32 && p->precision != 64)
     return fail(TLB_EINVAL, "precision must be 32 or 64");
-  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION)) return fail(TLB_EINVAL, "unknown flag");
+  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH))
+    return fail(TLB_EINVAL, "unknown flag");
   return TLB_OK;
 }
 
@@ -887,6 +952,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
 void tlb_destroy(tlb_grid* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
+  if (g->chunk_exec) (void)hipGraphExecDestroy(g->chunk_exec);
   (void)hipFree(g->rows);
   (void)hipFree(g->area);
   (void)hipFree(g->partial);

@@ -159,3 +159,24 @@ def test_spinodal_full_size_fp64_and_fp32(torch_cuda):
     e32f, e32p = rel_linf(f32, f_ref), rel_linf(p32, phi_ref)
     print(f"512x1280 fp32 after 2 steps: f {e32f:.2e} phi {e32p:.2e}", flush=True)
     assert e32f <= 1e-5 and e32p <= 1e-5
+
+
+def test_graph_replay_matches_plain_launches_bitwise(torch_cuda):
+    """tlb_step_n replays a prebuilt graph of 32 steps; with TLB_NO_GRAPH it launches each
+    kernel.  Several replays, with eager work and synchronisation between them, must give
+    bit-identical states."""
+    from paper_1904_10070_amd import TorusGrid, NO_GRAPH
+    p = inputs.TorusParams(1.0, 2.5, 40, 96, 0.5, 2e-3, 0.05, 0.3, 2e-4)
+    phi, n, ut, up = inputs.random_state(p, seed=17)
+    a = TorusGrid(p, precision=64)
+    b = TorusGrid(p.with_(flags=NO_GRAPH), precision=64)
+    for g in (a, b):
+        g.set_state(phi, n, ut, up)
+    for call in range(5):
+        a.step(64 + call)       # 2 graph replays + call plain steps
+        b.step(64 + call)
+        a.moments()
+        torch_cuda.cuda.synchronize()
+        fa, pa = a.get_state()
+        fb, pb = b.get_state()
+        assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb), call
