@@ -121,6 +121,17 @@ int32_t tlb_get_state(tlb_grid* grid, void* f, void* phi);
  * host array of 3 doubles.  Waits for the stream.  Returns TLB_ENONFINITE if out[2] > 0.  */
 int32_t tlb_invariants(tlb_grid* grid, double out[3]);
 
+/* Coarsening and stripe diagnostics of the current state, in FP64 with a fixed reduction
+ * order.  out (host, may be NULL; then nothing waits) receives out[0] = L_I, the interface
+ * length of section IV (every node whose phi changes sign towards its phi neighbour adds
+ * r dtheta, towards its theta neighbour (R + r cos theta_{q+1/2}) dphi, periodic), and
+ * out[1] = A_total = sum r J dtheta dphi, so that L_d = A_total / L_I (eq. cart_scaling_L0).
+ * phi_avg and p_avg (device arrays of n_theta doubles, may be NULL) receive the azimuthal
+ * averages of phi (eq. phiavg) and of the pressure p = n + A(-phi^2/2 + 3 phi^4/4)
+ * (eq. pbin; section III B measures the Laplace pressure with it).  Stream-ordered; waits
+ * for the stream only when out is non-NULL.  Errors: TLB_EINVAL, TLB_EHIP.                 */
+int32_t tlb_diagnostics(tlb_grid* grid, double out[2], double* phi_avg, double* p_avg);
+
 /* Release the handle and the library's own device memory (not the caller's buffers).      */
 void tlb_destroy(tlb_grid* grid);
 

@@ -61,6 +61,8 @@ def _lib(bits=64):
         lib.tlbref_geometry.restype = ctypes.c_int
         lib.tlbref_steps.argtypes = [vp]
         lib.tlbref_steps.restype = ctypes.c_int64
+        lib.tlbref_diagnostics.argtypes = [vp, _DP, _DP, _DP]
+        lib.tlbref_diagnostics.restype = ctypes.c_int
         lib.tlbref_real_bytes.argtypes = []
         lib.tlbref_real_bytes.restype = ctypes.c_int
         _LIBS[bits] = lib
@@ -161,6 +163,16 @@ class RefGrid:
         if rc != 0:
             raise ValueError(f"tlbref_rhs_terms failed ({rc})")
         return out
+
+    def diagnostics(self):
+        """dict(L_I, A_total, L_d, phi_avg[n_theta], p_avg[n_theta]) of the current state."""
+        out = np.zeros(2)
+        pa = np.zeros(self.shape[0])
+        pp = np.zeros(self.shape[0])
+        self.lib.tlbref_diagnostics(self._h, _ptr(out), _ptr(pa), _ptr(pp))
+        LI, A = float(out[0]), float(out[1])
+        return dict(L_I=LI, A_total=A, L_d=(A / LI if LI > 0 else float("inf")), phi_avg=pa,
+                    p_avg=pp)
 
     def geometry(self):
         nt = self.shape[0]

@@ -557,3 +557,44 @@ int tlbref_geometry(tlbref_grid* g, double* J, double* Jp, double* Jm, double* G
 int64_t tlbref_steps(const tlbref_grid* g) { return g ? g->steps : -1; }
 
 int tlbref_real_bytes(void) { return (int)sizeof(real); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Diagnostics of section IV and section III B, from the current state:
+ *   out[0] = L_I, the total interface length: every node (s, q) whose phi changes sign
+ *            towards (s+1, q) adds r dtheta, towards (s, q+1) adds (R + r cos theta_{q+1/2})
+ *            dphi (the description after eq. cart_scaling_L0; periodic wrap);
+ *   out[1] = A_total, the area sum r J dtheta dphi over all nodes, so L_d = A_total / L_I;
+ *   phi_avg[q] = azimuthal average of phi on row q (eq. phiavg);
+ *   p_avg[q] = azimuthal average of p = n + A(-phi^2/2 + 3 phi^4/4) on row q (eq. pbin).
+ * Any output pointer may be NULL.  All sums in double.                                      */
+int tlbref_diagnostics(tlbref_grid* g, double out[2], double* phi_avg, double* p_avg) {
+  if (!g) return TLBREF_EINVAL;
+  const double pi = acos(-1.0);
+  const double dth = 2.0 * pi / g->nt, dph = 2.0 * pi / g->np;
+  const int flat = (g->p.flags & TLBREF_FLAT) != 0;
+  double LI = 0.0, area = 0.0;
+  for (int q = 0; q < g->nt; ++q) {
+    int qp = wrap(q + 1, g->nt);
+    double J = flat ? g->p.R : g->p.R + g->p.r * cos(q * dth);
+    double Jh = flat ? g->p.R : g->p.R + g->p.r * cos((q + 0.5) * dth);
+    double rowphi = 0.0, rowp = 0.0;
+    for (int s = 0; s < g->np; ++s) {
+      int sp = wrap(s + 1, g->np);
+      double ph = (double)g->phi[IDX(g, q, s)];
+      if (ph * (double)g->phi[IDX(g, q, sp)] < 0.0) LI += g->p.r * dth;
+      if (ph * (double)g->phi[IDX(g, qp, s)] < 0.0) LI += Jh * dph;
+      double n = 0.0;
+      for (int k = 0; k < 16; ++k) n += (double)g->f[FIDX(g, k, q, s)];
+      rowphi += ph;
+      rowp += n + g->p.A * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
+    }
+    area += g->p.r * J * dth * dph * g->np;
+    if (phi_avg) phi_avg[q] = rowphi / g->np;
+    if (p_avg) p_avg[q] = rowp / g->np;
+  }
+  if (out) {
+    out[0] = LI;
+    out[1] = area;
+  }
+  return TLBREF_OK;
+}

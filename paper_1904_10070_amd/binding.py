@@ -23,7 +23,8 @@ CH_NO_ADVECTION = 2
 NO_GRAPH = 4
 
 EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
-            "tlb_get_state", "tlb_invariants", "tlb_destroy", "tlb_last_error")
+            "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",
+            "tlb_last_error")
 
 
 class TlbError(RuntimeError):
@@ -72,6 +73,8 @@ def load_library(path=None):
     lib.tlb_get_state.restype = i32
     lib.tlb_invariants.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.tlb_invariants.restype = i32
+    lib.tlb_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, vp]
+    lib.tlb_diagnostics.restype = i32
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_destroy.restype = None
     lib.tlb_last_error.argtypes = []
@@ -182,3 +185,17 @@ class TorusGrid:
         if rc not in (TLB_OK, TLB_ENONFINITE) or (check and rc != TLB_OK):
             _check(self.lib, rc, "tlb_invariants")
         return float(out[0]), float(out[1]), int(out[2])
+
+    def diagnostics(self, profiles=True):
+        """dict(L_I, A_total, L_d, phi_avg, p_avg): phi_avg / p_avg are float64 device tensors
+        of n_theta values (or None with profiles=False)."""
+        out = (ctypes.c_double * 2)()
+        pa = pp = None
+        if profiles:
+            pa = self.torch.empty(self.shape[0], dtype=self.torch.float64, device=self.device)
+            pp = self.torch.empty(self.shape[0], dtype=self.torch.float64, device=self.device)
+        _check(self.lib, self.lib.tlb_diagnostics(self._h, out, _ptr(pa), _ptr(pp)),
+               "tlb_diagnostics")
+        LI, A = float(out[0]), float(out[1])
+        return dict(L_I=LI, A_total=A, L_d=(A / LI if LI > 0 else float("inf")), phi_avg=pa,
+                    p_avg=pp)

@@ -631,6 +631,70 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, con
   }
 }
 
+// Diagnostics of sections III B and IV in FP64: per row q, the azimuthal averages of phi and of
+// p = n + A(-phi^2/2 + 3 phi^4/4); per block, the interface length (sign changes of phi towards
+// the phi neighbour count r dtheta, towards the theta neighbour (R + r cos theta_{q+1/2}) dphi)
+// and the area, as partials for tlb_reduce_final_kernel.
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const T* phi,
+                                                              const double* area,
+                                                              const double* half_len, double r_dth,
+                                                              double A, int nt, int np,
+                                                              int rows_per_block, double* phi_avg,
+                                                              double* p_avg, double* partial) {
+  __shared__ double s[3][RED_THREADS / 64];
+  const int q_begin = blockIdx.x * rows_per_block;
+  const int q_end = min(nt, q_begin + rows_per_block);
+  const long long plane = (long long)nt * np;
+  double len = 0.0, ar = 0.0;
+  for (int q = q_begin; q < q_end; ++q) {
+    const int qn = q + 1 == nt ? 0 : q + 1;
+    double rphi = 0.0, rp = 0.0;
+    for (int s0 = threadIdx.x; s0 < np; s0 += RED_THREADS) {
+      const long long x = (long long)q * np + s0;
+      const int se = s0 + 1 == np ? 0 : s0 + 1;
+      const double ph = (double)phi[x];
+      if (ph * (double)phi[(long long)q * np + se] < 0.0) len += r_dth;
+      if (ph * (double)phi[(long long)qn * np + s0] < 0.0) len += half_len[q];
+      double n = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) n += (double)f[k * plane + x];
+      rphi += ph;
+      rp += n + A * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
+    }
+    rphi = wave_sum(rphi);
+    rp = wave_sum(rp);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      s[0][w] = rphi;
+      s[1][w] = rp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int i = 0; i < RED_THREADS / 64; ++i) {
+        a += s[0][i];
+        b += s[1][i];
+      }
+      if (phi_avg) phi_avg[q] = a / np;
+      if (p_avg) p_avg[q] = b / np;
+    }
+    __syncthreads();
+    ar += area[q] * np;
+  }
+  len = wave_sum(len);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s[2][w] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < RED_THREADS / 64; ++i) t += s[2][i];
+    partial[3 * blockIdx.x + 0] = t;
+    partial[3 * blockIdx.x + 1] = ar;
+    partial[3 * blockIdx.x + 2] = 0.0;
+  }
+}
+
 __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_final_kernel(const double* partial,
                                                                       int nblocks,
                                                                       double* out) {
@@ -693,6 +757,7 @@ void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
     rc.inv_2Jdph = T(1.0 / (2.0 * J * dph));
     rc.inv_2rJdth = T(1.0 / (2.0 * p.r * J * dth));
     area[q] = p.r * J * dth * dph;
+    area[nt + q] = Jat(th + 0.5 * dth) * dph;
   }
 }
 
@@ -707,6 +772,7 @@ struct tlb_grid {
   void* rows;       // RowCoef<T>[nt]
   double* area;     // [nt]
   double* partial;  // [3 * red_blocks + 3]
+  double* half_len; // [nt]: (R + r cos theta_{q+1/2}) dphi, the length of a theta-face
   int red_blocks, rows_per_block;
   size_t elem;
   hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
@@ -855,6 +921,20 @@ int32_t reduce_t(tlb_grid* g) {
   return TLB_OK;
 }
 
+template <typename T>
+int32_t diag_t(tlb_grid* g, double* phi_avg, double* p_avg) {
+  const double dth = 2.0 * M_PI / g->p.n_theta;
+  hipLaunchKernelGGL(tlb_diag_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0, g->stream,
+                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]), g->area,
+                     g->half_len, g->p.r * dth, g->p.A, g->p.n_theta, g->p.n_phi,
+                     g->rows_per_block, phi_avg, p_avg, g->partial);
+  TLB_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(tlb_reduce_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream,
+                     g->partial, g->red_blocks, g->partial + 3 * g->red_blocks);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
 int32_t check_params(const tlb_params* p) {
   if (!p) return fail(TLB_EINVAL, "params is NULL");
   if (!(p->r > 0.0) || !std::isfinite(p->r)) return fail(TLB_EINVAL, "r must be > 0");
@@ -914,13 +994,15 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   const size_t row_bytes =
       params->precision == 64 ? sizeof(RowCoef<double>) : sizeof(RowCoef<float>);
   void* host_rows = std::malloc(row_bytes * nt);
-  double* host_area = static_cast<double*>(std::malloc(sizeof(double) * nt));
+  // area[q] in host_area[0..nt), theta-face length in host_area[nt..2nt)
+  double* host_area = static_cast<double*>(std::malloc(sizeof(double) * 2 * nt));
   auto cleanup = [&](int32_t code, const std::string& msg) {
     std::free(host_rows);
     std::free(host_area);
     if (g->rows) (void)hipFree(g->rows);
     if (g->area) (void)hipFree(g->area);
     if (g->partial) (void)hipFree(g->partial);
+    if (g->half_len) (void)hipFree(g->half_len);
     delete g;
     return fail(code, msg);
   };
@@ -935,11 +1017,15 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   if (e == hipSuccess)
     e = hipMalloc(reinterpret_cast<void**>(&g->partial),
                   sizeof(double) * (3 * g->red_blocks + 3));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->half_len), sizeof(double) * nt);
   if (e != hipSuccess)
     return cleanup(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipMemcpyAsync(g->rows, host_rows, row_bytes * nt, hipMemcpyHostToDevice, g->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(g->area, host_area, sizeof(double) * nt, hipMemcpyHostToDevice,
+                       g->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->half_len, host_area + nt, sizeof(double) * nt, hipMemcpyHostToDevice,
                        g->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   if (e != hipSuccess) return cleanup(TLB_EHIP, std::string("upload: ") + hipGetErrorString(e));
@@ -956,6 +1042,7 @@ void tlb_destroy(tlb_grid* g) {
   (void)hipFree(g->rows);
   (void)hipFree(g->area);
   (void)hipFree(g->partial);
+  (void)hipFree(g->half_len);
   delete g;
 }
 
@@ -1011,6 +1098,23 @@ int32_t tlb_invariants(tlb_grid* g, double out[3]) {
                                hipMemcpyDeviceToHost, g->stream));
   TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (out[2] > 0) return fail(TLB_ENONFINITE, "non-finite values in the state");
+  return TLB_OK;
+}
+
+int32_t tlb_diagnostics(tlb_grid* g, double out[2], double* phi_avg, double* p_avg) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  int32_t rc = g->p.precision == 64 ? diag_t<double>(g, phi_avg, p_avg)
+                                    : diag_t<float>(g, phi_avg, p_avg);
+  if (rc != TLB_OK) return rc;
+  if (out) {
+    double tmp[3];
+    TLB_HIP_CHECK(hipMemcpyAsync(tmp, g->partial + 3 * g->red_blocks, 3 * sizeof(double),
+                                 hipMemcpyDeviceToHost, g->stream));
+    TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
+    out[0] = tmp[0];
+    out[1] = tmp[1];
+  }
   return TLB_OK;
 }
 

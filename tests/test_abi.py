@@ -78,6 +78,7 @@ def test_null_handles_rejected(lib):
     assert lib.tlb_get_state(None, None, None) == binding.TLB_EINVAL
     out = (ctypes.c_double * 3)()
     assert lib.tlb_invariants(None, out) == binding.TLB_EINVAL
+    assert lib.tlb_diagnostics(None, out, None, None) == binding.TLB_EINVAL
     lib.tlb_destroy(None)
 
 
