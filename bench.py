@@ -65,6 +65,40 @@ def gpu_leg(p, precision, steps, warmup, seed=7, phi=None):
                 bytes_per_launch=bytes_launch)
 
 
+def ensemble_leg(steps, warmup):
+    """64 tori (inputs.ensemble_workload) in FP32: one fused launch per stage for the whole
+    ensemble (autotuned tile height) against the same grids stepped one after another."""
+    import torch
+    from paper_1904_10070_amd import TorusBatch, TorusGrid, inputs
+    params = inputs.ensemble_workload()
+    grids = []
+    for i, p in enumerate(params):
+        g = TorusGrid(p, precision=32)
+        g.set_state(inputs.spinodal_phi(p, seed=1000 + i), *inputs.rest_moments(p.n_theta, p.n_phi))
+        grids.append(g)
+    nodes = sum(p.n_theta * p.n_phi for p in params)
+    batch = TorusBatch(grids)
+    rows = batch.autotune()
+
+    def timed(fn):
+        fn(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_batch = timed(batch.step)
+    t_alone = timed(lambda k: [g.step(k) for g in grids])
+    batch.close()
+    for g in grids:
+        g.close()
+    return {"value": nodes / t_batch, "unit": "node-updates/s", "tori": len(params),
+            "nodes": nodes, "ms_per_step": t_batch * 1e3, "tile_rows": rows,
+            "separate_runs_value": nodes / t_alone, "speedup_vs_separate": t_alone / t_batch,
+            "steps": steps}
+
+
 def measured_traffic(key):
     """HBM bytes per launch of the stage kernel from the committed counter summary
     (profiles/stage_kernel_traffic.json), or None if the kernel source changed since."""
@@ -126,7 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
-    ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64"],
+    ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64",
+                                       "ensemble32"],
                     help="time a single workload/precision (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
@@ -154,6 +189,9 @@ def main():
         dt = (time.perf_counter() - t0) / 20
         print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": 4 * n,
                           "bytes_written": 4 * n, "gbs_read_plus_write": 8 * n / dt / 1e9}))
+        return
+    if args.only == "ensemble32":
+        print(json.dumps(ensemble_leg(args.steps, args.warmup)))
         return
     if args.only:
         wl, prec = args.only[:-2], int(args.only[-2:])
@@ -209,6 +247,7 @@ def main():
         d = gpu_leg(pd, 64, 2000, args.warmup, phi=inputs.drop_workload_phi(pd, seed=1))
         out["drop64x160_fp64"] = {"value": d["nups"], "unit": "node-updates/s",
                                   "ms_per_step": d["t_step"] * 1e3, "steps": 2000}
+        out["ensemble64_fp32"] = ensemble_leg(max(10, args.steps // 10), 5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -135,6 +135,32 @@ int32_t tlb_diagnostics(tlb_grid* grid, double out[2], double* phi_avg, double* 
 /* Release the handle and the library's own device memory (not the caller's buffers).      */
 void tlb_destroy(tlb_grid* grid);
 
+/* Tile height of the fused stage kernel: tiles of 64 (phi) x rows (theta) nodes, one block of
+ * 64 rows threads each; rows = 4, 8 (default) or 16.  Results do not depend on it (every node
+ * runs the same arithmetic); only speed does.  Errors: TLB_EINVAL.                          */
+int32_t tlb_set_tile_rows(tlb_grid* grid, int32_t rows);
+
+/* Autotuner: time the stage kernel for every tile height on this grid (stage-1 launches,
+ * which leave the state unchanged) and keep the fastest; *rows (may be NULL) receives it.
+ * Waits for the stream.  Errors: TLB_EINVAL, TLB_EHIP.                                     */
+int32_t tlb_autotune(tlb_grid* grid, int32_t* rows);
+
+/* Ensembles of tori (coarsening statistics over tori of different aspect ratios and grid
+ * sizes, section IV): tlb_batch_step_n advances every grid of the batch by n_steps with one
+ * persistent fused launch per Runge-Kutta stage covering the tiles of all grids (each grid
+ * keeps its own parameters, time step and buffers), replayed from a graph for runs of 32
+ * steps.  Each grid ends exactly (bit for bit) where tlb_step_n on it alone would.  The batch
+ * keeps pointers to the grids, which must outlive it and must not be stepped on their own
+ * between batch calls on different streams.  All grids must have the same precision.
+ * Errors: TLB_EINVAL (NULL, empty, mixed precision, duplicate), TLB_ENOMEM, TLB_EHIP.      */
+typedef struct tlb_batch tlb_batch;
+int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n_grids, void* hip_stream,
+                         tlb_batch** out);
+int32_t tlb_batch_step_n(tlb_batch* batch, int64_t n_steps);
+/* Autotuner of the batched launch (as tlb_autotune, over the whole ensemble).             */
+int32_t tlb_batch_autotune(tlb_batch* batch, int32_t* rows);
+void tlb_destroy_batch(tlb_batch* batch);
+
 /* Message of the last error on the calling thread ("" if none).  Owned by the library.   */
 const char* tlb_last_error(void);
 

@@ -24,7 +24,8 @@ NO_GRAPH = 4
 
 EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",
-            "tlb_last_error")
+            "tlb_last_error", "tlb_set_tile_rows", "tlb_autotune", "tlb_create_batch",
+            "tlb_batch_step_n", "tlb_batch_autotune", "tlb_destroy_batch")
 
 
 class TlbError(RuntimeError):
@@ -75,6 +76,18 @@ def load_library(path=None):
     lib.tlb_invariants.restype = i32
     lib.tlb_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, vp]
     lib.tlb_diagnostics.restype = i32
+    lib.tlb_set_tile_rows.argtypes = [vp, i32]
+    lib.tlb_set_tile_rows.restype = i32
+    lib.tlb_autotune.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.tlb_autotune.restype = i32
+    lib.tlb_create_batch.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(vp)]
+    lib.tlb_create_batch.restype = i32
+    lib.tlb_batch_step_n.argtypes = [vp, i64]
+    lib.tlb_batch_step_n.restype = i32
+    lib.tlb_batch_autotune.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.tlb_batch_autotune.restype = i32
+    lib.tlb_destroy_batch.argtypes = [vp]
+    lib.tlb_destroy_batch.restype = None
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_destroy.restype = None
     lib.tlb_last_error.argtypes = []
@@ -199,3 +212,48 @@ class TorusGrid:
         LI, A = float(out[0]), float(out[1])
         return dict(L_I=LI, A_total=A, L_d=(A / LI if LI > 0 else float("inf")), phi_avg=pa,
                     p_avg=pp)
+
+    def set_tile_rows(self, rows):
+        _check(self.lib, self.lib.tlb_set_tile_rows(self._h, int(rows)), "tlb_set_tile_rows")
+
+    def autotune(self):
+        rows = ctypes.c_int32()
+        _check(self.lib, self.lib.tlb_autotune(self._h, ctypes.byref(rows)), "tlb_autotune")
+        return rows.value
+
+
+class TorusBatch:
+    """An ensemble of TorusGrid objects advanced together by one fused launch per stage."""
+
+    def __init__(self, grids, stream=None):
+        import torch
+        self.lib = load_library()
+        self.grids = list(grids)
+        self.stream = stream if stream is not None else self.grids[0].stream
+        arr = (ctypes.c_void_p * len(self.grids))(*[g._h.value for g in self.grids])
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(self.lib, self.lib.tlb_create_batch(arr, len(self.grids),
+                                                   ctypes.c_void_p(self.stream.cuda_stream),
+                                                   ctypes.byref(h)), "tlb_create_batch")
+        self._h = h
+
+    def step(self, nsteps):
+        _check(self.lib, self.lib.tlb_batch_step_n(self._h, int(nsteps)), "tlb_batch_step_n")
+
+    def autotune(self):
+        rows = ctypes.c_int32()
+        _check(self.lib, self.lib.tlb_batch_autotune(self._h, ctypes.byref(rows)),
+               "tlb_batch_autotune")
+        return rows.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.tlb_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -94,22 +94,25 @@ __host__ __device__ __forceinline__ void static_for(F&& fn) {
 
 // ------------------------------------------------------------------------------------------
 // tile geometry of the stage kernel
-constexpr int TX = 64;           // nodes along phi per tile = wavefront width
-#ifndef TLB_TY
-#define TLB_TY 8
-#endif
-constexpr int TY = TLB_TY;       // nodes along theta per tile = wavefronts per block
-constexpr int HY = 3;            // population halo rows (UW5 needs 3 upwind, 2 downwind)
-constexpr int NT = TX * TY;      // 256 threads
-constexpr int NWAVE = NT / 64;
+constexpr int TX = 64;  // nodes along phi per tile = wavefront width
+constexpr int HY = 3;   // population halo rows (UW5 needs 3 upwind, 2 downwind)
 // LDS tiles hold rows of 72 elements: columns s0-4 .. s0+67, a 16-byte aligned window that
 // contains the 3-node phi halo of the populations and the 2-node halo of the order parameter.
 constexpr int LXT = TX + 8;
-constexpr int CX = 4;            // LDS column of the tile's first node
-constexpr int LY = TY + 2 * HY;  // population tile rows q0-3 .. q0+TY+2
-constexpr int PY = TY + 4;       // order-parameter tile rows q0-2 .. q0+TY+1
-constexpr int NRING = 2 * TX + 2 * TY;  // cross-shaped ring of 1 node
-static_assert(NRING <= NT, "ring nodes must fit one per thread");
+constexpr int CX = 4;   // LDS column of the tile's first node
+// A tile is TX x TY nodes, one wavefront per row; the tile height TY (4, 8 or 16) is chosen
+// per grid at run time (tlb_set_tile_rows / tlb_autotune).
+template <int TY_>
+struct Tile {
+  static constexpr int TY = TY_;
+  static constexpr int NT = TX * TY;            // threads per block
+  static constexpr int NWAVE = TY;
+  static constexpr int LY = TY + 2 * HY;        // population tile rows q0-3 .. q0+TY+2
+  static constexpr int PY = TY + 4;             // order-parameter tile rows q0-2 .. q0+TY+1
+  static constexpr int NRING = 2 * TX + 2 * TY; // cross-shaped ring of 1 node
+  static_assert(NRING <= NT, "ring nodes must fit one per thread");
+};
+constexpr int DEFAULT_TY = 8;
 
 // UW5 flux difference (face_{+1/2} - face_{-1/2}) for a positive velocity, offsets -3..+2;
 // the negative-velocity stencil is its mirror image with the sign flipped, offsets -2..+3.
@@ -209,8 +212,9 @@ constexpr int BUF_DWORD3 = 0x00020000;
 // [i NT + w c_i, i NT + (w+1) c_i) with c_i = ceil(units of instruction i / waves), lanes past
 // the tile masked off; every wave thus issues every instruction, so all waves count the same
 // number of outstanding copies per tile (the waits below rely on it).
-template <typename T, bool VEC, int ROWS, int R0>
+template <typename T, bool VEC, int ROWS, int R0, int NT>
 struct TileCopy {
+  static constexpr int NWAVE = NT / 64;
   static constexpr int UNIT = VEC ? 16 : 4;
   static constexpr int ROW_UNITS = LXT * (int)sizeof(T) / UNIT;
   static constexpr int UNITS = ROWS * ROW_UNITS;
@@ -297,11 +301,15 @@ struct Ring {
   static constexpr int D = sizeof(T) == 4 ? TLB_RING32 : TLB_RING64;
 };
 
-template <typename T, bool VEC>
-__global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
+// One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
+// described by `a`, by a block of Tile<TY>::NT threads.
+template <typename T, bool VEC, int TY>
+__device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, const int ty) {
+  using TL = Tile<TY>;
+  constexpr int NT = TL::NT, LY = TL::LY, PY = TL::PY, NRING = TL::NRING;
   constexpr int D = Ring<T>::D;
-  using CopyF = TileCopy<T, VEC, LY, -HY>;
-  using CopyPhi = TileCopy<T, VEC, PY, -2>;
+  using CopyF = TileCopy<T, VEC, LY, -HY, NT>;
+  using CopyPhi = TileCopy<T, VEC, PY, -2, NT>;
   constexpr int DW = CopyF::INSTR;
   constexpr int TILE_SLOTS = LY * LXT;
   static_assert(D >= 2 && D <= 8, "ring depth");
@@ -331,9 +339,6 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ly = wave;  // wavefront-uniform row of the tile
   const int nt = a.nt, np = a.np;
-  const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
-  int tx, ty;
-  band_tile(tile, a.ntx, a.nty, tx, ty);
   const int q0 = ty * TY, s0 = tx * TX;
   const int q = q0 + ly, s = s0 + lx;
   const bool active = (q < nt) && (s < np);
@@ -378,6 +383,10 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
 
   // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
+  // moments of this node and of the ring node, both summed population by population in the
+  // same order, so that a node's moments (and all that follows) do not depend on whether it
+  // is inside a tile or in a neighbour's ring -- results are independent of the tile shape
+  T n = T(0), nut = T(0), nup = T(0);
   T rn = T(0), rut = T(0), rup = T(0);
   const int cN = (ly + HY) * LXT + lx + CX;  // this node in the population tile
   const int cR = (ry + HY) * LXT + rx + CX;  // the ring node
@@ -397,6 +406,9 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
       cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
     const T* buf = slot(ic<k>{});
     f[k] = buf[cN];
+    n += f[k];
+    nut += T(vel(i)) * f[k];
+    nup += T(vel(j)) * f[k];
     // phi direction: sum_o uw5(o) f_{s+o}, upwind side by the sign of v_j
     T dph;
     if constexpr (j >= 2) {
@@ -438,21 +450,15 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
     // the end of the kernel and holds every stencil value of all 16 populations live
     pin_reg(adv[k]);
     pin_reg(f[k]);
+    pin_reg(n);
+    pin_reg(nut);
+    pin_reg(nup);
     pin_reg(rn);
     pin_reg(rut);
     pin_reg(rup);
   });
 
-  // ---- moments at the node; CH fluxes of the tile and the ring
-  T n = T(0), nut = T(0), nup = T(0);
-  static_for<0, 4>([&](auto ic_) {
-    constexpr int i = decltype(ic_)::value;
-    const T row = (f[4 * i] + f[4 * i + 1]) + (f[4 * i + 2] + f[4 * i + 3]);
-    const T col = (f[i] + f[4 + i]) + (f[8 + i] + f[12 + i]);
-    n += row;
-    nut += T(vel(i)) * row;
-    nup += T(vel(i)) * col;
-  });
+  // ---- CH fluxes of the tile and the ring
   const T inv_n = T(1) / n;
   const T ut = nut * inv_n, up = nup * inv_n;
   const T phc = sPhi[(ly + 2) * LXT + lx + CX];
@@ -522,6 +528,41 @@ __global__ __launch_bounds__(NT) void tlb_stage_kernel(StageArgs<T> a) {
       *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
     }
   });
+}
+
+template <typename T, bool VEC, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a) {
+  const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
+  int tx, ty;
+  band_tile(tile, a.ntx, a.nty, tx, ty);
+  stage_tile<T, VEC, TY>(a, tx, ty);
+}
+
+// One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
+// the stage arguments of grid g; tile_begin[g] is the first tile of grid g in the concatenated
+// tile order (tile_begin[n] = total).  XCD x owns a contiguous range of that order, which its
+// gridDim.x / 8 resident blocks walk with a stride, tile by tile.
+template <typename T, bool VEC, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
+    const StageArgs<T>* __restrict__ table, const int* __restrict__ tile_begin, int n, int stage) {
+  const int total = tile_begin[n];
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = gridDim.x >> 3;
+  const int full = total >> 3, rem = total & 7;
+  const int t0 = xcd * full + min(xcd, rem), cnt = full + (xcd < rem ? 1 : 0);
+  for (int i = local; i < cnt; i += per) {
+    const int t = t0 + i;
+    int lo = 0, hi = n - 1;  // the grid owning tile t: the last g with tile_begin[g] <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_begin[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const StageArgs<T> a = table[3 * lo + stage - 1];
+    int tx, ty;
+    band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
+    stage_tile<T, VEC, TY>(a, tx, ty);
+    __syncthreads();  // the next tile reuses the LDS tiles
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -775,7 +816,21 @@ struct tlb_grid {
   double* half_len; // [nt]: (R + r cos theta_{q+1/2}) dphi, the length of a theta-face
   int red_blocks, rows_per_block;
   size_t elem;
+  int ty;                     // tile height of the stage kernel (4, 8 or 16)
   hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
+  bool chunk_tried;
+};
+
+struct tlb_batch {
+  tlb_grid** grids;
+  int n;
+  int precision, ty, blocks;
+  bool vec;
+  hipStream_t stream;
+  void* table;      // StageArgs<T>[3 n] (device)
+  int* tile_begin;  // [n + 1] (device)
+  int total_tiles;
+  hipGraphExec_t chunk_exec;
   bool chunk_tried;
 };
 
@@ -796,7 +851,7 @@ StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   a.nt = g->p.n_theta;
   a.np = g->p.n_phi;
   a.ntx = (a.np + TX - 1) / TX;
-  a.nty = (a.nt + TY - 1) / TY;
+  a.nty = (a.nt + g->ty - 1) / g->ty;
   a.plane = (long long)a.nt * a.np;
   a.has_y0 = stage != 1;
   a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
@@ -805,25 +860,45 @@ StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   return a;
 }
 
-// the stage kernel variant for this grid: 16-byte copies need every 16-byte chunk of a row
-// inside one period of phi
+// 16-byte copies need every 16-byte chunk of a row inside one period of phi
+template <typename T>
+bool vec_ok(int n_phi) {
+  return n_phi % (16 / (int)sizeof(T)) == 0;
+}
+
+template <typename T, bool VEC>
+const void* stage_fn_ty(int ty) {
+  switch (ty) {
+    case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 4>);
+    case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 16>);
+    default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 8>);
+  }
+}
+
 template <typename T>
 const void* stage_fn(const tlb_grid* g) {
-  const bool vec = g->p.n_phi % (16 / (int)sizeof(T)) == 0;
-  return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true>)
-             : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false>);
+  return vec_ok<T>(g->p.n_phi) ? stage_fn_ty<T, true>(g->ty) : stage_fn_ty<T, false>(g->ty);
+}
+
+template <typename T, bool VEC>
+const void* batch_fn_ty(int ty) {
+  switch (ty) {
+    case 4: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 4>);
+    case 16: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 16>);
+    default: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 8>);
+  }
 }
 
 int stage_blocks(const tlb_grid* g) {
-  return ((g->p.n_phi + TX - 1) / TX) * ((g->p.n_theta + TY - 1) / TY);
+  return ((g->p.n_phi + TX - 1) / TX) * ((g->p.n_theta + g->ty - 1) / g->ty);
 }
 
 template <typename T>
 int32_t launch_stage(tlb_grid* g, int stage) {
   StageArgs<T> a = stage_args<T>(g, stage);
   void* params[] = {&a};
-  TLB_HIP_CHECK(hipLaunchKernel(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(NT), params, 0,
-                                g->stream));
+  TLB_HIP_CHECK(hipLaunchKernel(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(TX * g->ty), params,
+                                0, g->stream));
   return TLB_OK;
 }
 
@@ -832,34 +907,48 @@ int32_t launch_stage(tlb_grid* g, int stage) {
 // default stream -- and replayed with one launch.  Kernel nodes only.
 constexpr int GRAPH_CHUNK = 32;
 
-template <typename T>
-int32_t build_chunk_graph(tlb_grid* g) {
+// `make_params(st)` returns the kernel-argument array of stage st (1..3); the arrays must stay
+// valid until the graph is instantiated
+template <class MakeParams>
+hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_params,
+                       hipGraphExec_t* out) {
   hipGraph_t graph;
-  TLB_HIP_CHECK(hipGraphCreate(&graph, 0));
-  StageArgs<T> args[3] = {stage_args<T>(g, 1), stage_args<T>(g, 2), stage_args<T>(g, 3)};
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return e;
   hipGraphNode_t prev = nullptr;
-  hipError_t e = hipSuccess;
   for (int t = 0; t < GRAPH_CHUNK && e == hipSuccess; ++t)
-    for (int st = 0; st < 3 && e == hipSuccess; ++st) {
-      void* params[] = {&args[st]};
+    for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
       hipKernelNodeParams kp{};
-      kp.func = const_cast<void*>(stage_fn<T>(g));
-      kp.gridDim = dim3(stage_blocks(g));
-      kp.blockDim = dim3(NT);
+      kp.func = const_cast<void*>(fn);
+      kp.gridDim = grid;
+      kp.blockDim = block;
       kp.sharedMemBytes = 0;
-      kp.kernelParams = params;
+      kp.kernelParams = make_params(st);
       kp.extra = nullptr;
       hipGraphNode_t node;
       e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
       prev = node;
     }
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->chunk_exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) {
-    g->chunk_exec = nullptr;
-    return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
-  }
+  if (e != hipSuccess) *out = nullptr;
+  return e;
+}
+
+template <typename T>
+int32_t build_chunk_graph(tlb_grid* g) {
+  StageArgs<T> args[3] = {stage_args<T>(g, 1), stage_args<T>(g, 2), stage_args<T>(g, 3)};
+  void* params[3][1] = {{&args[0]}, {&args[1]}, {&args[2]}};
+  hipError_t e = build_chain(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(TX * g->ty),
+                             [&](int st) { return params[st - 1]; }, &g->chunk_exec);
+  if (e != hipSuccess) return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
   return TLB_OK;
+}
+
+void drop_graph(tlb_grid* g) {
+  if (g->chunk_exec) (void)hipGraphExecDestroy(g->chunk_exec);
+  g->chunk_exec = nullptr;
+  g->chunk_tried = false;
 }
 
 template <typename T>
@@ -881,6 +970,163 @@ int32_t step_n_t(tlb_grid* g, int64_t n) {
       if (rc != TLB_OK) return rc;
     }
   return TLB_OK;
+}
+
+// Time `reps` launches of `launch()` on `stream` (after one untimed launch), in milliseconds.
+template <class Launch>
+int32_t time_launches(hipStream_t stream, int reps, Launch launch, float* ms) {
+  hipEvent_t e0, e1;
+  TLB_HIP_CHECK(hipEventCreate(&e0));
+  TLB_HIP_CHECK(hipEventCreate(&e1));
+  int32_t rc = launch();
+  if (rc == TLB_OK) {
+    (void)hipEventRecord(e0, stream);
+    for (int i = 0; i < reps && rc == TLB_OK; ++i) rc = launch();
+    (void)hipEventRecord(e1, stream);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+constexpr int TILE_CHOICES[3] = {4, 8, 16};
+
+// Autotuner: time stage-1 launches (they read the state and write only the stage-1 scratch
+// copy, so the state is unchanged) for every tile height and keep the fastest.
+template <typename T>
+int32_t autotune_t(tlb_grid* g, int32_t* chosen) {
+  float best = -1.0f;
+  int best_ty = DEFAULT_TY;
+  for (int ty : TILE_CHOICES) {
+    g->ty = ty;
+    float ms = 0.0f;
+    int32_t rc = time_launches(g->stream, 5, [&]() { return launch_stage<T>(g, 1); }, &ms);
+    if (rc != TLB_OK) return rc;
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      best_ty = ty;
+    }
+  }
+  g->ty = best_ty;
+  drop_graph(g);
+  if (chosen) *chosen = best_ty;
+  return TLB_OK;
+}
+
+// ---- ensembles ------------------------------------------------------------------------------
+
+void drop_batch_graph(tlb_batch* b) {
+  if (b->chunk_exec) (void)hipGraphExecDestroy(b->chunk_exec);
+  b->chunk_exec = nullptr;
+  b->chunk_tried = false;
+}
+
+// (Re)build the argument table and the tile offsets of the batch for its tile height, and the
+// size of the persistent grid (blocks resident on the whole GPU at once, a multiple of 8).
+template <typename T>
+int32_t batch_setup_t(tlb_batch* b) {
+  std::string err;
+  StageArgs<T>* tab = static_cast<StageArgs<T>*>(std::malloc(sizeof(StageArgs<T>) * 3 * b->n));
+  int* tb = static_cast<int*>(std::malloc(sizeof(int) * (b->n + 1)));
+  if (!tab || !tb) {
+    std::free(tab);
+    std::free(tb);
+    return fail(TLB_ENOMEM, "host allocation failed");
+  }
+  long long total = 0;
+  for (int i = 0; i < b->n; ++i) {
+    tlb_grid tmp = *b->grids[i];
+    tmp.ty = b->ty;
+    for (int st = 1; st <= 3; ++st) tab[3 * i + st - 1] = stage_args<T>(&tmp, st);
+    tb[i] = (int)total;
+    total += stage_blocks(&tmp);
+  }
+  tb[b->n] = (int)total;
+  b->total_tiles = (int)total;
+  hipError_t e = hipMemcpyAsync(b->table, tab, sizeof(StageArgs<T>) * 3 * b->n,
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->tile_begin, tb, sizeof(int) * (b->n + 1), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  std::free(tab);
+  std::free(tb);
+  if (e != hipSuccess) return fail(TLB_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+  const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+  int dev = 0, cus = 0, per_cu = 0;
+  TLB_HIP_CHECK(hipGetDevice(&dev));
+  TLB_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  TLB_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TX * b->ty, 0));
+  const long long resident = (long long)cus * (per_cu > 0 ? per_cu : 1);
+  long long blocks = total < resident ? total : resident;
+  blocks = (blocks + 7) / 8 * 8;
+  b->blocks = (int)(blocks > 8 ? blocks : 8);
+  drop_batch_graph(b);
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t batch_launch_t(tlb_batch* b, int stage) {
+  const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+  const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
+  const int* tile_begin = b->tile_begin;
+  int n = b->n;
+  void* params[] = {&table, &tile_begin, &n, &stage};
+  TLB_HIP_CHECK(hipLaunchKernel(fn, dim3(b->blocks), dim3(TX * b->ty), params, 0, b->stream));
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t batch_step_t(tlb_batch* b, int64_t n) {
+  if (n >= GRAPH_CHUNK && !b->chunk_tried) {
+    b->chunk_tried = true;
+    const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+    const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
+    const int* tile_begin = b->tile_begin;
+    int nn = b->n;
+    int stages[3] = {1, 2, 3};
+    void* params[3][4] = {{&table, &tile_begin, &nn, &stages[0]},
+                          {&table, &tile_begin, &nn, &stages[1]},
+                          {&table, &tile_begin, &nn, &stages[2]}};
+    hipError_t e = build_chain(fn, dim3(b->blocks), dim3(TX * b->ty),
+                               [&](int st) { return params[st - 1]; }, &b->chunk_exec);
+    if (e != hipSuccess)
+      return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
+  }
+  int64_t done = 0;
+  if (n >= GRAPH_CHUNK && b->chunk_exec)
+    for (; done + GRAPH_CHUNK <= n; done += GRAPH_CHUNK)
+      TLB_HIP_CHECK(hipGraphLaunch(b->chunk_exec, b->stream));
+  for (; done < n; ++done)
+    for (int st = 1; st <= 3; ++st) {
+      int32_t rc = batch_launch_t<T>(b, st);
+      if (rc != TLB_OK) return rc;
+    }
+  return TLB_OK;
+}
+
+template <typename T>
+int32_t batch_autotune_t(tlb_batch* b, int32_t* chosen) {
+  float best = -1.0f;
+  int best_ty = DEFAULT_TY;
+  for (int ty : TILE_CHOICES) {
+    b->ty = ty;
+    int32_t rc = batch_setup_t<T>(b);
+    if (rc != TLB_OK) return rc;
+    float ms = 0.0f;
+    rc = time_launches(b->stream, 5, [&]() { return batch_launch_t<T>(b, 1); }, &ms);
+    if (rc != TLB_OK) return rc;
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      best_ty = ty;
+    }
+  }
+  b->ty = best_ty;
+  int32_t rc = batch_setup_t<T>(b);
+  if (chosen) *chosen = best_ty;
+  return rc;
 }
 
 template <typename T>
@@ -987,6 +1233,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   }
   g->stream = static_cast<hipStream_t>(hip_stream);
   g->elem = params->precision == 64 ? sizeof(double) : sizeof(float);
+  g->ty = DEFAULT_TY;
   const int nt = params->n_theta;
   g->rows_per_block = nt <= 512 ? 1 : (nt + 511) / 512;
   g->red_blocks = (nt + g->rows_per_block - 1) / g->rows_per_block;
@@ -1038,7 +1285,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
 void tlb_destroy(tlb_grid* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
-  if (g->chunk_exec) (void)hipGraphExecDestroy(g->chunk_exec);
+  drop_graph(g);
   (void)hipFree(g->rows);
   (void)hipFree(g->area);
   (void)hipFree(g->partial);
@@ -1099,6 +1346,90 @@ int32_t tlb_invariants(tlb_grid* g, double out[3]) {
   TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (out[2] > 0) return fail(TLB_ENONFINITE, "non-finite values in the state");
   return TLB_OK;
+}
+
+int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  if (rows != 4 && rows != 8 && rows != 16) return fail(TLB_EINVAL, "tile rows must be 4, 8 or 16");
+  if (g->ty != rows) {
+    g->ty = rows;
+    drop_graph(g);
+  }
+  return TLB_OK;
+}
+
+int32_t tlb_autotune(tlb_grid* g, int32_t* rows) {
+  g_last_error.clear();
+  if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  return g->p.precision == 64 ? autotune_t<double>(g, rows) : autotune_t<float>(g, rows);
+}
+
+int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tlb_batch** out) {
+  g_last_error.clear();
+  if (!out) return fail(TLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grids || n < 1) return fail(TLB_EINVAL, "a batch needs at least one grid");
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(TLB_EINVAL, "a grid of the batch is NULL");
+    if (grids[i]->p.precision != grids[0]->p.precision)
+      return fail(TLB_EINVAL, "all grids of a batch must have the same precision");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(TLB_EINVAL, "a grid appears twice in the batch");
+  }
+  tlb_batch* b = new (std::nothrow) tlb_batch{};
+  if (!b) return fail(TLB_ENOMEM, "host allocation failed");
+  b->grids = new (std::nothrow) tlb_grid*[n];
+  if (!b->grids) {
+    delete b;
+    return fail(TLB_ENOMEM, "host allocation failed");
+  }
+  b->n = n;
+  b->precision = grids[0]->p.precision;
+  b->ty = DEFAULT_TY;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->vec = true;
+  for (int i = 0; i < n; ++i) {
+    b->grids[i] = grids[i];
+    b->vec = b->vec && (b->precision == 64 ? vec_ok<double>(grids[i]->p.n_phi)
+                                           : vec_ok<float>(grids[i]->p.n_phi));
+  }
+  const size_t args_bytes = b->precision == 64 ? sizeof(StageArgs<double>) : sizeof(StageArgs<float>);
+  hipError_t e = hipMalloc(&b->table, args_bytes * 3 * n);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->tile_begin), sizeof(int) * (n + 1));
+  int32_t rc = TLB_OK;
+  if (e != hipSuccess) rc = fail(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (rc == TLB_OK)
+    rc = b->precision == 64 ? batch_setup_t<double>(b) : batch_setup_t<float>(b);
+  if (rc != TLB_OK) {
+    tlb_destroy_batch(b);
+    return rc;
+  }
+  *out = b;
+  return TLB_OK;
+}
+
+int32_t tlb_batch_step_n(tlb_batch* b, int64_t n_steps) {
+  g_last_error.clear();
+  if (!b) return fail(TLB_EINVAL, "batch is NULL");
+  if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
+  return b->precision == 64 ? batch_step_t<double>(b, n_steps) : batch_step_t<float>(b, n_steps);
+}
+
+int32_t tlb_batch_autotune(tlb_batch* b, int32_t* rows) {
+  g_last_error.clear();
+  if (!b) return fail(TLB_EINVAL, "batch is NULL");
+  return b->precision == 64 ? batch_autotune_t<double>(b, rows) : batch_autotune_t<float>(b, rows);
+}
+
+void tlb_destroy_batch(tlb_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  drop_batch_graph(b);
+  if (b->table) (void)hipFree(b->table);
+  if (b->tile_begin) (void)hipFree(b->tile_begin);
+  delete[] b->grids;
+  delete b;
 }
 
 int32_t tlb_diagnostics(tlb_grid* g, double out[2], double* phi_avg, double* p_avg) {

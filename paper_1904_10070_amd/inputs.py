@@ -163,3 +163,34 @@ def random_state(p, seed=0, amp_phi=0.5, amp_u=0.05, amp_n=0.05):
     ut = amp_u * rng.uniform(-1, 1, T.shape)
     up = amp_u * rng.uniform(-1, 1, T.shape)
     return phi, n, ut, up
+
+
+# -- time step and ensembles -----------------------------------------------------------------------
+
+def stable_dt(p, safety=0.5):
+    """A time step below the explicit stability limits of the discrete step: upwind advection
+    at CFL 1 over the smallest spacings, BGK relaxation (2.5 tau, the SSP-RK3 real-axis limit)
+    and the Cahn-Hilliard operator (biharmonic M kappa S^2 plus M A 2 S with
+    S = 4/h_theta^2 + 4/h_phi^2 at the inner equator, against the same 2.51 limit)."""
+    v_max = math.sqrt(3.0 + math.sqrt(6.0))
+    h_t = p.r * 2 * math.pi / p.n_theta
+    h_p = (p.R - p.r) * 2 * math.pi / p.n_phi
+    dt_adv = 1.0 / (v_max * (1.0 / h_t + 1.0 / h_p))
+    dt_bgk = 2.5 * p.tau
+    S = 4.0 / h_t ** 2 + 4.0 / h_p ** 2
+    dt_ch = 2.51 / (p.M * p.kappa * S * S + 2.0 * p.M * abs(p.A) * S + 1e-300)
+    return safety * min(dt_adv, dt_bgk, dt_ch)
+
+
+def ensemble_workload(n=64, seed=4):
+    """n tori for coarsening statistics: r = 1, R uniform in [1.5, 5], N_theta from
+    {128, 192, ..., 512} and N_phi = 2 N_theta (seeded), interface width by the three-cell
+    rule, M = 2.5e-3, tau = 0.6, each with half its stability limit as time step."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        R = float(rng.uniform(1.5, 5.0))
+        nt = int(rng.choice(np.arange(128, 513, 64)))
+        p = params_three_cells(1.0, R, nt, 2 * nt, A=0.5, M=2.5e-3, tau=0.6, dt=1.0)
+        out.append(p.with_(dt=stable_dt(p)))
+    return out
