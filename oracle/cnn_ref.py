@@ -61,17 +61,6 @@ def pack(layers):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
 
 
-def init_params(seed, arch=ARCH, last_gain=0.1):
-    """He-normal weights (std sqrt(2 / fan_in)), zero biases, last layer scaled by last_gain;
-    returned as FP32 (the master precision)."""
-    rng = np.random.default_rng(seed)
-    layers = []
-    for l, (ci, co) in enumerate(arch):
-        std = math.sqrt(2.0 / (9 * ci)) * (last_gain if l == len(arch) - 1 else 1.0)
-        layers.append((rng.normal(0.0, std, size=(co, 9, ci)), np.zeros(co)))
-    return pack(layers).astype(np.float32)
-
-
 # -- bfloat16 ----------------------------------------------------------------------------------
 
 def bf16(x):

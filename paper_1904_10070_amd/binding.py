@@ -1,4 +1,4 @@
-"""Thin ctypes binding of the C interface in include/tlb.h.
+"""Thin ctypes binding of the C interface in include/tlb.h and include/tlb_learn.h.
 
 Argument marshalling only: PyTorch provides the device buffers and the stream, and every step
 of the method runs in the HIP kernels of libtlb.so.  There is no fallback: if the library has
@@ -25,7 +25,12 @@ NO_GRAPH = 4
 EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",
             "tlb_last_error", "tlb_set_tile_rows", "tlb_autotune", "tlb_create_batch",
-            "tlb_batch_step_n", "tlb_batch_autotune", "tlb_destroy_batch")
+            "tlb_batch_step_n", "tlb_batch_autotune", "tlb_destroy_batch",
+            "tlb_cnn_create", "tlb_cnn_destroy", "tlb_cnn_set_params", "tlb_cnn_get_params",
+            "tlb_cnn_forward", "tlb_cnn_gradient", "tlb_cnn_train_step", "tlb_learn_stats",
+            "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n")
+
+CNN_PARAMS = 30660
 
 
 class TlbError(RuntimeError):
@@ -44,6 +49,19 @@ class Params(ctypes.Structure):
 
 class Buffers(ctypes.Structure):
     _fields_ = [("f", ctypes.c_void_p * 3), ("phi", ctypes.c_void_p * 3)]
+
+
+class CnnDesc(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_double), ("R", ctypes.c_double),
+                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
+                ("out_scale", ctypes.c_float * 4), ("loss_weight", ctypes.c_float * 4)]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", ctypes.c_int32)]
 
 
 _LIB = None
@@ -92,6 +110,24 @@ def load_library(path=None):
     lib.tlb_destroy.restype = None
     lib.tlb_last_error.argtypes = []
     lib.tlb_last_error.restype = ctypes.c_char_p
+    dp, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+    lib.tlb_cnn_create.argtypes = [ctypes.POINTER(CnnDesc), vp, ctypes.POINTER(vp)]
+    lib.tlb_cnn_destroy.argtypes = [vp]
+    lib.tlb_cnn_destroy.restype = None
+    lib.tlb_cnn_set_params.argtypes = [vp, fp]
+    lib.tlb_cnn_get_params.argtypes = [vp, fp]
+    lib.tlb_cnn_forward.argtypes = [vp, vp, vp, i32, vp]
+    lib.tlb_cnn_gradient.argtypes = [vp, vp, vp, vp, i32, dp, fp]
+    lib.tlb_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(Adam), dp]
+    lib.tlb_learn_stats.argtypes = [vp, i64, vp, dp]
+    lib.tlb_restrict.argtypes = [vp, vp]
+    lib.tlb_learn_pair.argtypes = [vp, vp, vp, vp]
+    lib.tlb_apply_correction.argtypes = [vp, vp]
+    lib.tlb_learned_step_n.argtypes = [vp, vp, i64]
+    for name in ("tlb_cnn_create", "tlb_cnn_set_params", "tlb_cnn_get_params",
+                 "tlb_cnn_forward", "tlb_cnn_gradient", "tlb_cnn_train_step", "tlb_learn_stats",
+                 "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n"):
+        getattr(lib, name).restype = i32
     _LIB = lib
     return lib
 
@@ -257,3 +293,149 @@ class TorusBatch:
             self.close()
         except Exception:
             pass
+
+
+# -- the learned coarse-step correction (include/tlb_learn.h) ---------------------------------------
+
+def _f32(t, shape=None):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), "float32 device tensor"
+    if shape is not None:
+        assert tuple(t.shape[-len(shape):]) == tuple(shape), (tuple(t.shape), shape)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _idx(idx):
+    import torch
+    if idx is None:
+        return None, None
+    t = torch.as_tensor(idx, dtype=torch.int32).to("cuda").contiguous()
+    return t, ctypes.c_void_p(t.data_ptr())
+
+
+class CoarseCNN:
+    """The periodic five-layer 3x3 network of tlb_learn.h, trained and run by libtlb's kernels.
+
+    r, R, n_theta, n_phi: the torus and grid it runs on; max_batch: largest batch of samples;
+    in_shift / in_scale (4 each), out_scale (4), loss_weight (4): as in tlb_cnn_desc."""
+
+    def __init__(self, r, R, n_theta, n_phi, max_batch, in_shift, in_scale, out_scale,
+                 loss_weight=(1.0, 1.0, 1.0, 1.0), stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the network runs only in the HIP kernels")
+        self.shape = (int(n_theta), int(n_phi))
+        self.max_batch = int(max_batch)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        d = CnnDesc(float(r), float(R), int(n_theta), int(n_phi), int(max_batch), 0)
+        for name, vals in (("in_shift", in_shift), ("in_scale", in_scale),
+                           ("out_scale", out_scale), ("loss_weight", loss_weight)):
+            arr = getattr(d, name)
+            for c in range(4):
+                arr[c] = float(vals[c])
+        self.desc = d
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(self.lib, self.lib.tlb_cnn_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(h)), "tlb_cnn_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.tlb_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (CNN_PARAMS,)
+        _check(self.lib, self.lib.tlb_cnn_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "tlb_cnn_set_params")
+
+    def get_params(self):
+        p = np.zeros(CNN_PARAMS, dtype=np.float32)
+        _check(self.lib, self.lib.tlb_cnn_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "tlb_cnn_get_params")
+        return p
+
+    def forward(self, moments, idx=None, n=None):
+        """moments: float32 device tensor [*, n_theta, n_phi, 4]; returns corrections [n, ..., 4]."""
+        t, ip = _idx(idx)
+        n = int(len(idx) if idx is not None else (n if n is not None else moments.shape[0]))
+        out = self.torch.empty((n,) + self.shape + (4,), dtype=self.torch.float32, device="cuda")
+        _check(self.lib, self.lib.tlb_cnn_forward(self._h, _f32(moments, self.shape + (4,)), ip, n,
+                                                  _f32(out)), "tlb_cnn_forward")
+        self._keep = t
+        return out
+
+    def gradient(self, moments, targets, idx=None, n=None):
+        """(loss, gradient as float32 numpy array) on a batch; weights unchanged."""
+        t, ip = _idx(idx)
+        n = int(len(idx) if idx is not None else (n if n is not None else moments.shape[0]))
+        loss = ctypes.c_double()
+        g = np.zeros(CNN_PARAMS, dtype=np.float32)
+        _check(self.lib, self.lib.tlb_cnn_gradient(self._h, _f32(moments, self.shape + (4,)),
+                                                   _f32(targets, self.shape + (4,)), ip, n,
+                                                   ctypes.byref(loss),
+                                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "tlb_cnn_gradient")
+        return loss.value, g
+
+    def train_step(self, moments, targets, idx, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                   want_loss=False):
+        t, ip = _idx(idx)
+        adam = Adam(float(lr), float(beta1), float(beta2), float(eps), int(step))
+        loss = ctypes.c_double()
+        _check(self.lib, self.lib.tlb_cnn_train_step(self._h, _f32(moments, self.shape + (4,)),
+                                                     _f32(targets, self.shape + (4,)), ip, len(idx),
+                                                     ctypes.byref(adam),
+                                                     ctypes.byref(loss) if want_loss else None),
+               "tlb_cnn_train_step")
+        self._keep = t
+        return loss.value if want_loss else None
+
+
+def learn_stats(data, stream=None):
+    """(sum, sum of squares) of each of the 4 channels of a float32 device tensor [..., 4]."""
+    import torch
+    lib = load_library()
+    out = (ctypes.c_double * 8)()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib, lib.tlb_learn_stats(_f32(data), int(data.numel() // 4), ctypes.c_void_p(s.cuda_stream), out),
+           "tlb_learn_stats")
+    return np.array(out[:4]), np.array(out[4:])
+
+
+def restrict(fine, coarse):
+    """Overwrite coarse's state with the full-weighting restriction of fine's (tlb_restrict)."""
+    _check(fine.lib, fine.lib.tlb_restrict(fine._h, coarse._h), "tlb_restrict")
+
+
+def learn_pair(grid, truth=None, moments=None, targets=None):
+    """Moments of grid's state [nt, np, 4], and with truth also moments(truth) - moments(grid)."""
+    import torch
+    shape = grid.shape + (4,)
+    m = moments if moments is not None else torch.empty(shape, dtype=torch.float32, device="cuda")
+    y = None
+    if truth is not None:
+        y = targets if targets is not None else torch.empty(shape, dtype=torch.float32, device="cuda")
+    _check(grid.lib, grid.lib.tlb_learn_pair(grid._h, truth._h if truth is not None else None,
+                                             _f32(m, shape), _f32(y, shape) if y is not None else None),
+           "tlb_learn_pair")
+    return m, y
+
+
+def apply_correction(grid, corrections):
+    _check(grid.lib, grid.lib.tlb_apply_correction(grid._h, _f32(corrections, grid.shape + (4,))),
+           "tlb_apply_correction")
+
+
+def learned_step(grid, net, nsteps):
+    _check(grid.lib, grid.lib.tlb_learned_step_n(grid._h, net._h, int(nsteps)), "tlb_learned_step_n")

@@ -1,11 +1,12 @@
-"""Compile the HIP library for gfx950 into paper_1904_10070_amd/libtlb.so (in-tree)."""
+"""Compile the HIP library (the torus step and the learned correction) for gfx950 into
+paper_1904_10070_amd/libtlb.so (in-tree)."""
 import os
 import subprocess
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "tlb.hip")
+SRCS = [os.path.join(PKG, "csrc", "tlb.hip"), os.path.join(PKG, "csrc", "learn.hip")]
 LIB = os.path.join(PKG, "libtlb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -18,7 +19,7 @@ FLAGS = [
 
 
 def build(verbose=False, extra=(), out=LIB):
-    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), SRC, "-o", out + ".tmp"]
+    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), *SRCS, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

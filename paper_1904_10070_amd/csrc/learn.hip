@@ -1,0 +1,1322 @@
+// learn.hip -- learned correction of a coarsened torus step on MI355X (gfx950): the periodic
+// five-layer 3x3 network of include/tlb_learn.h, its training (loss, back-propagation, Adam)
+// and the glue between torus grids and the network (restriction, moments and targets, the
+// equilibrium-based correction).
+//
+// Convolutions are implicit GEMMs on the matrix cores, v_mfma_f32_16x16x32_bf16: 16 output
+// channels x 16 nodes per instruction, 32-long products (one tap of 32 channels, or four taps
+// of 8 channels), bfloat16 operands, FP32 accumulation.
+//   forward / input gradient  one wavefront = 16 consecutive nodes of a row x all output
+//                             channels; weights are staged once per workgroup in LDS in
+//                             fragment order (each lane reads its 16 bytes); the node
+//                             operand is one 16-byte load per lane and tap straight from the
+//                             channel-last activation tensor.  The input gradient is the same
+//                             kernel with the weights transposed and the taps mirrored.
+//   weight gradient           one workgroup = strips of 64 nodes of a row; the error signal
+//                             and the nine shifted input tiles are transposed into LDS so that
+//                             the contraction over nodes reads 8 consecutive nodes per lane;
+//                             per-workgroup partial sums are added in a fixed order (FP64).
+// Activations are bfloat16, channel-last [sample][theta][phi][channel].
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tlb.h"
+#include "tlb_internal.h"
+#include "tlb_learn.h"
+
+#define LRN_HIP_CHECK(call)                                                             \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return tlbi_fail(TLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+// ------------------------------------------------------------------------------------------
+// the architecture
+
+constexpr int NL = TLB_CNN_LAYERS;
+constexpr int WIDTH = TLB_CNN_WIDTH;
+constexpr int L_CIN[NL] = {6, 32, 32, 32, 32};   // real input channels
+constexpr int L_COUT[NL] = {32, 32, 32, 32, 4};  // real output channels
+// storage channels of the tensor each layer reads and of its error signal
+constexpr int L_CIS[NL] = {8, 32, 32, 32, 32};
+constexpr int L_COS[NL] = {32, 32, 32, 32, 8};
+
+constexpr int layer_params(int l) { return L_COUT[l] * 9 * L_CIN[l] + L_COUT[l]; }
+constexpr int layer_offset(int l) { return l == 0 ? 0 : layer_offset(l - 1) + layer_params(l - 1); }
+static_assert(layer_offset(NL) == TLB_CNN_PARAMS, "parameter count");
+
+// ------------------------------------------------------------------------------------------
+// bfloat16
+
+__device__ __forceinline__ u16 to_bf16(float x) { return __builtin_bit_cast(u16, (__bf16)x); }
+__device__ __forceinline__ float from_bf16(u16 b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ bf16x8 zero_frag() {
+  bf16x8 z;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+  return z;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i = i % n;
+  return i < 0 ? i + n : i;
+}
+
+// The eight input features of a node from its raw moments (phi, n, u_theta, u_phi).
+struct Features {
+  float shift[4], scale[4];
+  float r;
+  const float* Jrow;  // [n_theta]: R + r cos theta_q
+};
+
+__device__ __forceinline__ void features_f(const Features& F, float4 m, int row, float x[8]) {
+  x[0] = (m.x - F.shift[0]) * F.scale[0];
+  x[1] = (m.y - F.shift[1]) * F.scale[1];
+  x[2] = (m.z - F.shift[2]) * F.scale[2];
+  x[3] = (m.w - F.shift[3]) * F.scale[3];
+  x[4] = F.r;
+  x[5] = F.Jrow[row];
+  x[6] = 0.0f;
+  x[7] = 0.0f;
+}
+
+__device__ __forceinline__ bf16x8 features(const Features& F, float4 m, int row) {
+  float x[8];
+  features_f(F, m, row, x);
+  bf16x8 v;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (__bf16)x[i];
+  return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// convolution (forward and input gradient)
+
+enum { IN_BF32 = 0, IN_BF8 = 1, IN_MOM = 2 };       // 32-channel / 8-channel bf16, raw moments
+enum { EPI_RELU = 0, EPI_OUT = 1, EPI_MASK = 2 };   // bias+ReLU, bias (FP32 out), ReLU mask
+
+struct ConvArgs {
+  const void* in;        // bf16 [n][H][W][32 or 8], or float [*][H][W][4] moments
+  const int32_t* idx;    // moments: sample of each batch slot (NULL = identity)
+  const bf16x8* w;       // weight fragments [kc][cob][64 lanes]
+  const float* bias;     // [c_out] (EPI_RELU, EPI_OUT)
+  const u16* mask;       // EPI_MASK: activation whose positive entries pass, [n][H][W][32]
+  void* out;             // bf16 [n][H][W][32], or float [n][H][W][4] (EPI_OUT)
+  Features F;
+  int n, H, W, xt, tiles;  // xt = ceil(W / 16) node groups per row; tiles = n H xt
+};
+
+constexpr int CONV_THREADS = 256;
+constexpr int CONV_WAVES = CONV_THREADS / 64;
+
+template <int IN, int COB, int EPI>
+__global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
+  constexpr int KC = IN == IN_BF32 ? 9 : 3;  // 32-long product chunks
+  __shared__ bf16x8 sw[KC * COB * 64];
+  for (int i = threadIdx.x; i < KC * COB * 64; i += CONV_THREADS) sw[i] = a.w[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int px = lane & 15, g = lane >> 4;
+  for (int t = blockIdx.x * CONV_WAVES + wave; t < a.tiles; t += gridDim.x * CONV_WAVES) {
+    const int xb = t % a.xt;
+    const int rest = t / a.xt;
+    const int y = rest % a.H, n = rest / a.H;
+    const int x = xb * 16 + px;
+    f32x4 acc[COB];
+#pragma unroll
+    for (int b = 0; b < COB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      // this lane's 8 products of chunk c: tap c with channels 8g..8g+7 (32-channel input),
+      // or tap 4c+g with all 8 channels (8-channel input; taps 9..11 are zero padding)
+      const int tap = IN == IN_BF32 ? c : 4 * c + g;
+      bf16x8 bfrag = zero_frag();
+      if (tap < 9) {
+        const int yy = wrap(y + tap / 3 - 1, a.H);
+        const int xx = wrap(x + tap % 3 - 1, a.W);
+        const size_t pix = ((size_t)n * a.H + yy) * a.W + xx;
+        if constexpr (IN == IN_BF32) {
+          bfrag = static_cast<const bf16x8*>(a.in)[pix * 4 + g];
+        } else if constexpr (IN == IN_BF8) {
+          bfrag = static_cast<const bf16x8*>(a.in)[pix];
+        } else {
+          const int smp = a.idx ? a.idx[n] : n;
+          const size_t mp = ((size_t)smp * a.H + yy) * a.W + xx;
+          bfrag = features(a.F, static_cast<const float4*>(a.in)[mp], yy);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < COB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sw[(c * COB + b) * 64 + lane], bfrag,
+                                                         acc[b], 0, 0, 0);
+    }
+    if (x >= a.W) continue;
+    // lane holds node x, output channels 16 b + 4 g + i
+    const size_t opix = ((size_t)n * a.H + y) * a.W + x;
+    if constexpr (EPI == EPI_OUT) {
+      if (g == 0) {
+        float4 o;
+        o.x = acc[0][0] + a.bias[0];
+        o.y = acc[0][1] + a.bias[1];
+        o.z = acc[0][2] + a.bias[2];
+        o.w = acc[0][3] + a.bias[3];
+        static_cast<float4*>(a.out)[opix] = o;
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < COB; ++b) {
+        const int co = 16 * b + 4 * g;
+        float v[4];
+        if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[b][i] + a.bias[co + i], 0.0f);
+        } else {
+          const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + opix * 32 + co);
+          const u16 m4[4] = {(u16)(mk.x & 0xFFFF), (u16)(mk.x >> 16), (u16)(mk.y & 0xFFFF),
+                             (u16)(mk.y >> 16)};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = from_bf16(m4[i]) > 0.0f ? acc[b][i] : 0.0f;
+        }
+        uint2 st;
+        st.x = (unsigned)to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
+        st.y = (unsigned)to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2*>(static_cast<u16*>(a.out) + opix * 32 + co) = st;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// weight gradient: dW[o][t][i] = sum over nodes of e[node][o] a[node + offset(t)][i]
+
+constexpr int WG_PITCH = 72;  // LDS row pitch (bf16): 64 nodes + 8 keeps rows 16-byte aligned
+constexpr int WG_THREADS = 256;
+
+struct WgradArgs {
+  const u16* e;        // error signal bf16 [n][H][W][COS]
+  const void* a;       // layer input: bf16 [n][H][W][CIS], or float moments [*][H][W][4]
+  const int32_t* idx;  // moments: sample of each batch slot (NULL = identity)
+  float* partial;      // [gridDim.x][COS * 9 * CIS + COS]
+  Features F;
+  int n, H, W, xs, strips;  // xs = ceil(W / 64) strips per row; strips = n H xs
+};
+
+template <int CIS, int COS, bool MOM>
+__global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
+  constexpr int CIB = (CIS + 15) / 16, COB = (COS + 15) / 16;
+  constexpr int NF = 9 * COB * CIB;            // 16 x 16 output fragments
+  constexpr int FPW = (NF + 3) / 4;            // fragments per wavefront
+  __shared__ __attribute__((aligned(16))) u16 sE[COS * WG_PITCH];
+  __shared__ __attribute__((aligned(16))) u16 sA[9 * CIS * WG_PITCH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int px = lane & 15, g = lane >> 4;
+  f32x4 acc[FPW];
+#pragma unroll
+  for (int k = 0; k < FPW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;
+  const int s0 = (int)((long long)blockIdx.x * a.strips / gridDim.x);
+  const int s1 = (int)((long long)(blockIdx.x + 1) * a.strips / gridDim.x);
+  for (int s = s0; s < s1; ++s) {
+    const int xb = s % a.xs;
+    const int rest = s / a.xs;
+    const int y = rest % a.H, n = rest / a.H;
+    const int x0 = xb * 64;
+    // error tile, transposed: sE[o][j] = e[n][y][x0 + j][o], zero beyond the row's end
+    for (int u = threadIdx.x; u < (COS / 8) * 64; u += WG_THREADS) {
+      const int j = u & 63, c8 = u >> 6;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (x0 + j < a.W)
+        v = *reinterpret_cast<const uint4*>(a.e + (((size_t)n * a.H + y) * a.W + x0 + j) * COS +
+                                            8 * c8);
+      const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        sE[(8 * c8 + i) * WG_PITCH + j] = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
+    }
+    // input tiles of the nine taps, transposed: sA[t][i][j] = a[n][y + dy][x0 + j + dx][i]
+    for (int u = threadIdx.x; u < 9 * (CIS / 8) * 64; u += WG_THREADS) {
+      const int j = u & 63;
+      const int r2 = u >> 6;
+      const int c8 = r2 % (CIS / 8), t = r2 / (CIS / 8);
+      const int yy = wrap(y + t / 3 - 1, a.H);
+      const int xx = wrap(x0 + j + t % 3 - 1, a.W);
+      u16 v[8];
+      if constexpr (MOM) {
+        const int smp = a.idx ? a.idx[n] : n;
+        const float4 m = static_cast<const float4*>(a.a)[((size_t)smp * a.H + yy) * a.W + xx];
+        float x[8];
+        features_f(a.F, m, yy, x);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = to_bf16(x[i]);
+      } else {
+        const uint4 q = *reinterpret_cast<const uint4*>(
+            static_cast<const u16*>(a.a) + (((size_t)n * a.H + yy) * a.W + xx) * CIS + 8 * c8);
+        const unsigned w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sA[(t * CIS + 8 * c8 + i) * WG_PITCH + j] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FPW; ++k) {
+      const int f = wave + 4 * k;
+      if (f < NF) {
+        const int t = f / (COB * CIB), bc = (f / CIB) % COB, bi = f % CIB;
+        const int co = 16 * bc + px, ci = 16 * bi + px;
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+          const bf16x8 A = co < COS ? *reinterpret_cast<const bf16x8*>(
+                                          &sE[co * WG_PITCH + 32 * kc + 8 * g])
+                                    : zero_frag();
+          const bf16x8 B = ci < CIS ? *reinterpret_cast<const bf16x8*>(
+                                          &sA[(t * CIS + ci) * WG_PITCH + 32 * kc + 8 * g])
+                                    : zero_frag();
+          acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[k], 0, 0, 0);
+        }
+      }
+    }
+    if (threadIdx.x < COS)
+      for (int j = 0; j < 64; ++j) bsum += from_bf16(sE[threadIdx.x * WG_PITCH + j]);
+    __syncthreads();
+  }
+  float* out = a.partial + (size_t)blockIdx.x * (COS * 9 * CIS + COS);
+#pragma unroll
+  for (int k = 0; k < FPW; ++k) {
+    const int f = wave + 4 * k;
+    if (f < NF) {
+      const int t = f / (COB * CIB), bc = (f / CIB) % COB, bi = f % CIB;
+      const int ci = 16 * bi + px;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = 16 * bc + 4 * g + i;
+        if (co < COS && ci < CIS) out[(co * 9 + t) * CIS + ci] = acc[k][i];
+      }
+    }
+  }
+  if (threadIdx.x < COS) out[COS * 9 * CIS + threadIdx.x] = bsum;
+}
+
+// per-workgroup partial sums -> gradient of one layer's weights, fixed order, FP64 sums
+struct GradArgs {
+  const float* partial;
+  float* grad;  // the layer's slice of the flat gradient
+  int blocks, cis, cos_s, cin, cout;
+  double scale;
+};
+
+__global__ __launch_bounds__(256) void grad_reduce_kernel(GradArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nw = a.cout * 9 * a.cin;
+  if (p >= nw + a.cout) return;
+  int src;
+  if (p < nw) {
+    const int co = p / (9 * a.cin), rem = p % (9 * a.cin);
+    src = (co * 9 + rem / a.cin) * a.cis + rem % a.cin;
+  } else {
+    src = a.cos_s * 9 * a.cis + (p - nw);
+  }
+  const size_t stride = (size_t)a.cos_s * 9 * a.cis + a.cos_s;
+  double s = 0.0;
+  for (int b = 0; b < a.blocks; ++b) s += (double)a.partial[b * stride + src];
+  a.grad[p] = (float)(s * a.scale);
+}
+
+// ------------------------------------------------------------------------------------------
+// loss and the last layer's error signal
+
+constexpr int RED = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
+}
+
+struct LossArgs {
+  const float* z;        // [n][HW][4]
+  const float* y;        // targets [*][HW][4]
+  const int32_t* idx;
+  u16* e;                // [n][HW][8]
+  double* partial;       // [gridDim.x]
+  long long hw, total;   // nodes per sample, n * hw
+  float inv_scale[4], w[4];
+};
+
+__global__ __launch_bounds__(RED) void loss_kernel(LossArgs a) {
+  __shared__ double sh[RED / 64];
+  const long long i = (long long)blockIdx.x * RED + threadIdx.x;
+  double l = 0.0;
+  if (i < a.total) {
+    const long long n = i / a.hw, p = i - n * a.hw;
+    const long long smp = a.idx ? a.idx[n] : n;
+    const float4 z = reinterpret_cast<const float4*>(a.z)[i];
+    const float4 y = reinterpret_cast<const float4*>(a.y)[smp * a.hw + p];
+    const float d[4] = {z.x - y.x * a.inv_scale[0], z.y - y.y * a.inv_scale[1],
+                        z.z - y.z * a.inv_scale[2], z.w - y.w * a.inv_scale[3]};
+    u16 e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      e[c] = to_bf16(a.w[c] * d[c]);
+      l += (double)a.w[c] * (double)d[c] * (double)d[c];
+    }
+    uint4 st;
+    st.x = (unsigned)e[0] | ((unsigned)e[1] << 16);
+    st.y = (unsigned)e[2] | ((unsigned)e[3] << 16);
+    st.z = 0;
+    st.w = 0;
+    reinterpret_cast<uint4*>(a.e)[i] = st;
+  }
+  const double t = block_sum(l, sh);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = t;
+}
+
+struct SumArgs {
+  const double* partial;
+  double* out;
+  int blocks, width;  // out[c] = sum_b partial[b * width + c] * scale
+  double scale;
+};
+
+__global__ __launch_bounds__(64) void sum_partials_kernel(SumArgs a) {
+  const int c = threadIdx.x;
+  if (c >= a.width) return;
+  double s = 0.0;
+  for (int b = 0; b < a.blocks; ++b) s += a.partial[(size_t)b * a.width + c];
+  a.out[c] = s * a.scale;
+}
+
+// network output times the output scale
+struct ScaleArgs {
+  const float* z;
+  float* out;
+  long long count;  // nodes
+  float s[4];
+};
+
+__global__ __launch_bounds__(256) void scale_kernel(ScaleArgs a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.count) return;
+  const float4 z = reinterpret_cast<const float4*>(a.z)[i];
+  reinterpret_cast<float4*>(a.out)[i] = make_float4(z.x * a.s[0], z.y * a.s[1], z.z * a.s[2], z.w * a.s[3]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Adam and the bf16 weight fragments
+
+struct AdamArgs {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int count;
+  float lr, b1, b2, eps, c1, c2;  // c = 1 - beta^step
+};
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.count) return;
+  const float g = a.g[i];
+  const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+  const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+  a.m[i] = m;
+  a.v[i] = v;
+  a.p[i] -= a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+}
+
+// Fragment order of a weight operand: slot ((c * cob + b) * 64 + lane) * 8 + i holds the
+// weight of GEMM row 16 b + lane % 16 and product index k = 32 c + 8 (lane / 16) + i, where
+// k is (tap c, channel k % 32) for 32-channel operands and (tap 4c + lane/16, channel i) for
+// 8-channel ones.  Forward: rows are output channels, W[row][tap][ch].  Input gradient: rows
+// are input channels, taps mirrored, W[ch][8 - tap][row].
+struct FragArgs {
+  const float* W;  // the layer's W[c_out][9][c_in]
+  u16* out;
+  int slots, cob, wide, transpose, cin, cout;
+};
+
+__global__ __launch_bounds__(256) void frag_kernel(FragArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.slots) return;
+  const int i = s & 7, lane = (s >> 3) & 63;
+  const int b = (s >> 9) % a.cob, c = (s >> 9) / a.cob;
+  const int row = 16 * b + (lane & 15), g = lane >> 4;
+  const int tap = a.wide ? c : 4 * c + g;
+  const int ch = a.wide ? 8 * g + i : i;
+  float v = 0.0f;
+  if (tap < 9) {
+    if (!a.transpose) {
+      if (row < a.cout && ch < a.cin) v = a.W[(row * 9 + tap) * a.cin + ch];
+    } else {
+      if (row < a.cin && ch < a.cout) v = a.W[(ch * 9 + (8 - tap)) * a.cin + row];
+    }
+  }
+  a.out[s] = to_bf16(v);
+}
+
+// ------------------------------------------------------------------------------------------
+// torus grid <-> network
+
+template <typename T>
+struct MomArgs {
+  const T* f;
+  const T* phi;
+  const T* f2;     // truth grid (NULL: moments only)
+  const T* phi2;
+  float* m;        // [HW][4]
+  float* y;        // [HW][4]
+  long long plane;
+};
+
+template <typename T>
+__device__ __forceinline__ void node_moments(const T* f, const T* phi, long long plane,
+                                             long long x, double out[4]) {
+  double n = 0.0, nut = 0.0, nup = 0.0;
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double fk = (double)f[k * plane + x];
+    n += fk;
+    nut += vel(k >> 2) * fk;
+    nup += vel(k & 3) * fk;
+  });
+  out[0] = (double)phi[x];
+  out[1] = n;
+  out[2] = nut / n;
+  out[3] = nup / n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void moments_pair_kernel(MomArgs<T> a) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.plane) return;
+  double m[4];
+  node_moments(a.f, a.phi, a.plane, x, m);
+  reinterpret_cast<float4*>(a.m)[x] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
+  if (a.f2) {
+    double t[4];
+    node_moments(a.f2, a.phi2, a.plane, x, t);
+    reinterpret_cast<float4*>(a.y)[x] = make_float4((float)(t[0] - m[0]), (float)(t[1] - m[1]),
+                                                    (float)(t[2] - m[2]), (float)(t[3] - m[3]));
+  }
+}
+
+// area-weighted sums of the phi and n corrections, one block per theta row
+struct ProjArgs {
+  const float* d;       // corrections [HW][4] (times scale)
+  const double* area;   // [H]
+  double* partial;      // [H][3]: sum a dphi, sum a dn, sum a
+  int W;
+  float scale0, scale1;
+};
+
+__global__ __launch_bounds__(RED) void proj_kernel(ProjArgs a) {
+  __shared__ double sh[RED / 64];
+  const int q = blockIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int s = threadIdx.x; s < a.W; s += RED) {
+    const float4 d = reinterpret_cast<const float4*>(a.d)[(size_t)q * a.W + s];
+    s0 += (double)(d.x * a.scale0);
+    s1 += (double)(d.y * a.scale1);
+  }
+  const double ar = a.area[q];
+  const double t0 = block_sum(s0, sh);
+  const double t1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    a.partial[3 * q + 0] = ar * t0;
+    a.partial[3 * q + 1] = ar * t1;
+    a.partial[3 * q + 2] = ar * a.W;
+  }
+}
+
+template <typename T>
+struct ApplyArgs {
+  T* f;
+  T* phi;
+  const float* d;           // corrections [HW][4], times scale
+  const double* partial;    // [H][3]
+  int H;
+  long long plane;
+  float scale[4];
+};
+
+template <typename T>
+__device__ __forceinline__ T feq_k(int i, int j, T n, T ut, T up) {
+  const T c0 = T(1) - T(0.5) * (ut * ut + up * up);
+  const T xi = T(vel(i)) * ut + T(vel(j)) * up;
+  return (n * T(wgt(i) * wgt(j))) * (c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0))));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void apply_kernel(ApplyArgs<T> a) {
+  __shared__ double mean[2];
+  if (threadIdx.x < 2) {
+    double s = 0.0, ar = 0.0;
+    for (int q = 0; q < a.H; ++q) {
+      s += a.partial[3 * q + threadIdx.x];
+      ar += a.partial[3 * q + 2];
+    }
+    mean[threadIdx.x] = s / ar;
+  }
+  __syncthreads();
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.plane) return;
+  const float4 d = reinterpret_cast<const float4*>(a.d)[x];
+  const T dphi = T((double)(d.x * a.scale[0]) - mean[0]);
+  const T dn = T((double)(d.y * a.scale[1]) - mean[1]);
+  const T dut = T(d.z * a.scale[2]), dup = T(d.w * a.scale[3]);
+  T fk[16];
+  T n = T(0), nut = T(0), nup = T(0);
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    fk[k] = a.f[k * a.plane + x];
+    n += fk[k];
+    nut += T(vel(k >> 2)) * fk[k];
+    nup += T(vel(k & 3)) * fk[k];
+  });
+  const T ut = nut / n, up = nup / n;
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    a.f[k * a.plane + x] =
+        fk[k] + (feq_k<T>(k >> 2, k & 3, n + dn, ut + dut, up + dup) - feq_k<T>(k >> 2, k & 3, n, ut, up));
+  });
+  a.phi[x] += dphi;
+}
+
+// full-weighting restriction by an even factor k, J-weighted along theta
+template <typename T>
+struct RestrictArgs {
+  const T* f;
+  const T* phi;
+  T* fc;
+  T* phic;
+  const double* area;  // fine rows, proportional to J
+  int Hf, Wf, Hc, Wc, k;
+  long long plane_f, plane_c;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void restrict_kernel(RestrictArgs<T> a) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.plane_c) return;
+  const int Q = (int)(x / a.Wc), S = (int)(x - (long long)Q * a.Wc);
+  const int h = a.k / 2;
+  double rw[33];   // k <= 32
+  int rq[33];
+  double den = 0.0;
+  for (int d = -h; d <= h; ++d) {
+    const int q = wrap(a.k * Q + d, a.Hf);
+    const double w = (d == -h || d == h) ? 0.5 : 1.0;
+    rq[d + h] = q;
+    rw[d + h] = w * a.area[q];
+    den += rw[d + h];
+  }
+  den *= (double)a.k;  // the phi weights sum to k
+  for (int fld = 0; fld < 17; ++fld) {
+    const T* src = fld < 16 ? a.f + fld * a.plane_f : a.phi;
+    double acc = 0.0;
+    for (int d = 0; d <= 2 * h; ++d) {
+      const T* row = src + (size_t)rq[d] * a.Wf;
+      double racc = 0.0;
+      for (int e = -h; e <= h; ++e) {
+        const double w = (e == -h || e == h) ? 0.5 : 1.0;
+        racc += w * (double)row[wrap(a.k * S + e, a.Wf)];
+      }
+      acc += rw[d] * racc;
+    }
+    T* dst = fld < 16 ? a.fc + fld * a.plane_c : a.phic;
+    dst[x] = T(acc / den);
+  }
+}
+
+// sums of x and x^2 per channel of float[count][4]
+struct StatArgs {
+  const float* d;
+  long long count;
+  double* partial;  // [gridDim.x][8]
+};
+
+__global__ __launch_bounds__(RED) void stats_kernel(StatArgs a) {
+  __shared__ double sh[RED / 64];
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long i = (long long)blockIdx.x * RED + threadIdx.x; i < a.count;
+       i += (long long)gridDim.x * RED) {
+    const float4 v = reinterpret_cast<const float4*>(a.d)[i];
+    const double c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      s[j] += c[j];
+      s[4 + j] += c[j] * c[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double t = block_sum(s[j], sh);
+    if (threadIdx.x == 0) a.partial[(size_t)blockIdx.x * 8 + j] = t;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host side
+
+constexpr int WG_MAX_BLOCKS = 1024;
+constexpr int CONV_MAX_BLOCKS = 4096;
+constexpr int LEARN_GRAPH_CHUNK = 32;
+
+template <class Args>
+tlbi_launch make_launch(const void* fn, dim3 grid, dim3 block, const Args& args) {
+  static_assert(sizeof(Args) <= sizeof(tlbi_launch::args), "argument block");
+  tlbi_launch l;
+  l.fn = fn;
+  l.grid = grid;
+  l.block = block;
+  std::memcpy(l.args, &args, sizeof(Args));
+  return l;
+}
+
+int32_t run(const tlbi_launch& l, hipStream_t stream) {
+  void* p[] = {const_cast<unsigned char*>(l.args)};
+  LRN_HIP_CHECK(hipLaunchKernel(l.fn, l.grid, l.block, p, 0, stream));
+  return TLB_OK;
+}
+
+int32_t run_all(const std::vector<tlbi_launch>& seq, hipStream_t stream) {
+  for (const tlbi_launch& l : seq) {
+    int32_t rc = run(l, stream);
+    if (rc != TLB_OK) return rc;
+  }
+  return TLB_OK;
+}
+
+int blocks_for(long long n, int threads) { return (int)((n + threads - 1) / threads); }
+
+}  // namespace
+
+struct tlb_cnn {
+  tlb_cnn_desc d;
+  hipStream_t stream;
+  int H, W, B;
+  long long HW;
+  float* params;
+  float* grad;
+  float* mom;
+  float* vel;
+  u16* wf[NL];  // forward fragments
+  u16* wd[NL];  // input-gradient fragments (layers 1..4)
+  u16* act[4];
+  float* z;
+  u16* e4;
+  u16* eA;
+  u16* eB;
+  float* partial;      // weight-gradient partials
+  double* red;         // loss partials / statistics partials
+  double* scalars;     // [8]: loss, statistics
+  float* Jrow;
+  float* mbuf;         // moments of the grid being corrected [HW][4]
+  double* proj;        // [H][3]
+  int red_blocks;
+  // graph of LEARN_GRAPH_CHUNK learned steps, bound to one grid's buffers and tile shape
+  hipGraphExec_t chunk_exec;
+  const tlb_grid* chunk_grid;
+  void* chunk_key[7];
+};
+
+namespace {
+
+int frag_slots(int l, bool transpose) {
+  if (!transpose) {
+    const int kc = L_CIS[l] == 32 ? 9 : 3;
+    const int cob = (L_COUT[l] + 15) / 16;
+    return kc * cob * 64 * 8;
+  }
+  const int kc = L_COS[l] == 32 ? 9 : 3;
+  const int cob = (L_CIN[l] + 15) / 16;
+  return kc * cob * 64 * 8;
+}
+
+Features make_features(const tlb_cnn* net) {
+  Features F;
+  for (int c = 0; c < 4; ++c) {
+    F.shift[c] = net->d.in_shift[c];
+    F.scale[c] = net->d.in_scale[c];
+  }
+  F.r = (float)net->d.r;
+  F.Jrow = net->Jrow;
+  return F;
+}
+
+const void* conv_fn(int in, int cob, int epi) {
+  if (in == IN_MOM) return reinterpret_cast<const void*>(&conv_kernel<IN_MOM, 2, EPI_RELU>);
+  if (in == IN_BF8) return reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_MASK>);
+  if (epi == EPI_OUT) return reinterpret_cast<const void*>(&conv_kernel<IN_BF32, 1, EPI_OUT>);
+  if (epi == EPI_MASK) return reinterpret_cast<const void*>(&conv_kernel<IN_BF32, 2, EPI_MASK>);
+  (void)cob;
+  return reinterpret_cast<const void*>(&conv_kernel<IN_BF32, 2, EPI_RELU>);
+}
+
+tlbi_launch conv_launch(const tlb_cnn* net, int in, int cob, int epi, const void* src,
+                        const int32_t* idx, const u16* w, const float* bias, const u16* mask,
+                        void* out, int n) {
+  ConvArgs a{};
+  a.in = src;
+  a.idx = idx;
+  a.w = reinterpret_cast<const bf16x8*>(w);
+  a.bias = bias;
+  a.mask = mask;
+  a.out = out;
+  a.F = make_features(net);
+  a.n = n;
+  a.H = net->H;
+  a.W = net->W;
+  a.xt = (net->W + 15) / 16;
+  a.tiles = n * net->H * a.xt;
+  int blocks = blocks_for(a.tiles, CONV_WAVES);
+  if (blocks > CONV_MAX_BLOCKS) blocks = CONV_MAX_BLOCKS;
+  return make_launch(conv_fn(in, cob, epi), dim3(blocks), dim3(CONV_THREADS), a);
+}
+
+const float* bias_of(const tlb_cnn* net, int l) {
+  return net->params + layer_offset(l) + L_COUT[l] * 9 * L_CIN[l];
+}
+
+// forward of n samples: moments (sample idx[i]) -> act[0..3] -> z
+void forward_seq(const tlb_cnn* net, const float* moments, const int32_t* idx, int n,
+                 std::vector<tlbi_launch>& seq) {
+  seq.push_back(conv_launch(net, IN_MOM, 2, EPI_RELU, moments, idx, net->wf[0], bias_of(net, 0),
+                            nullptr, net->act[0], n));
+  for (int l = 1; l < 4; ++l)
+    seq.push_back(conv_launch(net, IN_BF32, 2, EPI_RELU, net->act[l - 1], nullptr, net->wf[l],
+                              bias_of(net, l), nullptr, net->act[l], n));
+  seq.push_back(conv_launch(net, IN_BF32, 1, EPI_OUT, net->act[3], nullptr, net->wf[4],
+                            bias_of(net, 4), nullptr, net->z, n));
+}
+
+const void* wgrad_fn(int l) {
+  if (l == 0) return reinterpret_cast<const void*>(&wgrad_kernel<8, 32, true>);
+  if (l == 4) return reinterpret_cast<const void*>(&wgrad_kernel<32, 8, false>);
+  return reinterpret_cast<const void*>(&wgrad_kernel<32, 32, false>);
+}
+
+// loss, back-propagation and the gradient of every layer into net->grad
+void backward_seq(const tlb_cnn* net, const float* moments, const float* targets,
+                  const int32_t* idx, int n, std::vector<tlbi_launch>& seq) {
+  LossArgs la{};
+  la.z = net->z;
+  la.y = targets;
+  la.idx = idx;
+  la.e = net->e4;
+  la.partial = net->red;
+  la.hw = net->HW;
+  la.total = (long long)n * net->HW;
+  for (int c = 0; c < 4; ++c) {
+    la.inv_scale[c] = 1.0f / net->d.out_scale[c];
+    la.w[c] = net->d.loss_weight[c];
+  }
+  const int lblocks = blocks_for(la.total, RED);
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&loss_kernel), dim3(lblocks), dim3(RED), la));
+  SumArgs sa{net->red, net->scalars, lblocks, 1, 1.0 / (4.0 * (double)la.total)};
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(64), sa));
+
+  const double scale = 2.0 / (4.0 * (double)la.total);
+  const u16* e = net->e4;
+  for (int l = NL - 1; l >= 0; --l) {
+    WgradArgs wa{};
+    wa.e = e;
+    wa.a = l == 0 ? static_cast<const void*>(moments) : static_cast<const void*>(net->act[l - 1]);
+    wa.idx = l == 0 ? idx : nullptr;
+    wa.partial = net->partial;
+    wa.F = make_features(net);
+    wa.n = n;
+    wa.H = net->H;
+    wa.W = net->W;
+    wa.xs = (net->W + 63) / 64;
+    wa.strips = n * net->H * wa.xs;
+    const int wblocks = wa.strips < WG_MAX_BLOCKS ? wa.strips : WG_MAX_BLOCKS;
+    seq.push_back(make_launch(wgrad_fn(l), dim3(wblocks), dim3(WG_THREADS), wa));
+    GradArgs ga{net->partial, net->grad + layer_offset(l), wblocks, L_CIS[l], L_COS[l], L_CIN[l],
+                L_COUT[l], scale};
+    seq.push_back(make_launch(reinterpret_cast<const void*>(&grad_reduce_kernel),
+                              dim3(blocks_for(layer_params(l), 256)), dim3(256), ga));
+    if (l > 0) {
+      // error signals alternate between two buffers: layer 4 -> eA, 3 -> eB, 2 -> eA, ...
+      u16* next = (l == 4 || e == net->eB) ? net->eA : net->eB;
+      seq.push_back(conv_launch(net, l == 4 ? IN_BF8 : IN_BF32, 2, EPI_MASK, e, nullptr,
+                                net->wd[l], nullptr, net->act[l - 1], next, n));
+      e = next;
+    }
+  }
+}
+
+void frags_seq(const tlb_cnn* net, std::vector<tlbi_launch>& seq) {
+  for (int l = 0; l < NL; ++l)
+    for (int tr = 0; tr < (l > 0 ? 2 : 1); ++tr) {
+      FragArgs fa{};
+      fa.W = net->params + layer_offset(l);
+      fa.out = tr ? net->wd[l] : net->wf[l];
+      fa.slots = frag_slots(l, tr);
+      fa.transpose = tr;
+      fa.cin = L_CIN[l];
+      fa.cout = L_COUT[l];
+      fa.cob = tr ? (L_CIN[l] + 15) / 16 : (L_COUT[l] + 15) / 16;
+      fa.wide = tr ? (L_COS[l] == 32) : (L_CIS[l] == 32);
+      seq.push_back(make_launch(reinterpret_cast<const void*>(&frag_kernel),
+                                dim3(blocks_for(fa.slots, 256)), dim3(256), fa));
+    }
+}
+
+int32_t check_batch(const tlb_cnn* net, const float* moments, int32_t n) {
+  if (!net) return tlbi_fail(TLB_EINVAL, "network is NULL");
+  if (!moments) return tlbi_fail(TLB_EINVAL, "moments is NULL");
+  if (n < 1 || n > net->B) return tlbi_fail(TLB_EINVAL, "batch size out of range [1, max_batch]");
+  return TLB_OK;
+}
+
+template <typename T>
+void pair_launch(const tlb_grid* g, const tlb_grid* truth, float* m, float* y,
+                 std::vector<tlbi_launch>& seq) {
+  MomArgs<T> a{};
+  a.f = static_cast<const T*>(g->f[0]);
+  a.phi = static_cast<const T*>(g->phi[0]);
+  a.f2 = truth ? static_cast<const T*>(truth->f[0]) : nullptr;
+  a.phi2 = truth ? static_cast<const T*>(truth->phi[0]) : nullptr;
+  a.m = m;
+  a.y = y;
+  a.plane = (long long)g->p.n_theta * g->p.n_phi;
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&moments_pair_kernel<T>),
+                            dim3(blocks_for(a.plane, 256)), dim3(256), a));
+}
+
+template <typename T>
+void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* proj,
+                    std::vector<tlbi_launch>& seq) {
+  ProjArgs pa{d, g->area, proj, g->p.n_phi, scale[0], scale[1]};
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&proj_kernel), dim3(g->p.n_theta),
+                            dim3(RED), pa));
+  ApplyArgs<T> aa{};
+  aa.f = static_cast<T*>(g->f[0]);
+  aa.phi = static_cast<T*>(g->phi[0]);
+  aa.d = d;
+  aa.partial = proj;
+  aa.H = g->p.n_theta;
+  aa.plane = (long long)g->p.n_theta * g->p.n_phi;
+  for (int c = 0; c < 4; ++c) aa.scale[c] = scale[c];
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&apply_kernel<T>),
+                            dim3(blocks_for(aa.plane, 256)), dim3(256), aa));
+}
+
+// one learned step of grid g: three stage launches, moments, network, correction
+void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) {
+  for (int st = 1; st <= 3; ++st) {
+    tlbi_launch l;
+    tlbi_stage_launch(g, st, &l);
+    seq.push_back(l);
+  }
+  if (g->p.precision == 64)
+    pair_launch<double>(g, nullptr, net->mbuf, nullptr, seq);
+  else
+    pair_launch<float>(g, nullptr, net->mbuf, nullptr, seq);
+  forward_seq(net, net->mbuf, nullptr, 1, seq);
+  if (g->p.precision == 64)
+    apply_launches<double>(g, net->z, net->d.out_scale, net->proj, seq);
+  else
+    apply_launches<float>(g, net->z, net->d.out_scale, net->proj, seq);
+}
+
+void drop_learn_graph(tlb_cnn* net) {
+  if (net->chunk_exec) (void)hipGraphExecDestroy(net->chunk_exec);
+  net->chunk_exec = nullptr;
+  net->chunk_grid = nullptr;
+}
+
+int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
+  drop_learn_graph(net);
+  std::vector<tlbi_launch> one;
+  learned_step_seq(g, net, one);
+  hipGraph_t graph;
+  LRN_HIP_CHECK(hipGraphCreate(&graph, 0));
+  // argument pointers stay valid until the graph is instantiated
+  std::vector<void*> argp(one.size());
+  for (size_t i = 0; i < one.size(); ++i) argp[i] = one[i].args;
+  hipError_t e = hipSuccess;
+  hipGraphNode_t prev = nullptr;
+  for (int t = 0; t < LEARN_GRAPH_CHUNK && e == hipSuccess; ++t)
+    for (size_t i = 0; i < one.size() && e == hipSuccess; ++i) {
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(one[i].fn);
+      kp.gridDim = one[i].grid;
+      kp.blockDim = one[i].block;
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = &argp[i];
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      prev = node;
+    }
+  if (e == hipSuccess) e = hipGraphInstantiate(&net->chunk_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    net->chunk_exec = nullptr;
+    return tlbi_fail(TLB_EHIP, std::string("learned-step graph: ") + hipGetErrorString(e));
+  }
+  net->chunk_grid = g;
+  void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
+                  reinterpret_cast<void*>((intptr_t)g->ty)};
+  std::memcpy(net->chunk_key, key, sizeof(key));
+  return TLB_OK;
+}
+
+bool graph_matches(const tlb_cnn* net, const tlb_grid* g) {
+  if (!net->chunk_exec || net->chunk_grid != g) return false;
+  void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
+                  reinterpret_cast<void*>((intptr_t)g->ty)};
+  return std::memcmp(net->chunk_key, key, sizeof(key)) == 0;
+}
+
+void free_net(tlb_cnn* net) {
+  void* bufs[] = {net->params, net->grad, net->mom, net->vel, net->z, net->e4, net->eA,
+                  net->eB, net->partial, net->red, net->scalars, net->Jrow, net->mbuf, net->proj};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int l = 0; l < NL; ++l) {
+    if (net->wf[l]) (void)hipFree(net->wf[l]);
+    if (net->wd[l]) (void)hipFree(net->wd[l]);
+  }
+  for (int l = 0; l < 4; ++l)
+    if (net->act[l]) (void)hipFree(net->act[l]);
+  drop_learn_graph(net);
+  delete net;
+}
+
+bool finite_nonzero(float x) { return std::isfinite(x) && x != 0.0f; }
+
+int32_t check_grid(const tlb_grid* g, const char* what) {
+  if (!g) return tlbi_fail(TLB_EINVAL, std::string(what) + " is NULL");
+  return TLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out) {
+  if (!out) return tlbi_fail(TLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return tlbi_fail(TLB_EINVAL, "desc is NULL");
+  const tlb_cnn_desc& d = *desc;
+  if (!(d.r > 0.0) || !(d.R > d.r) || !std::isfinite(d.R))
+    return tlbi_fail(TLB_EINVAL, "radii must satisfy 0 < r < R");
+  if (d.n_theta < 1 || d.n_phi < 1 || (long long)d.n_theta * d.n_phi > (1LL << 26))
+    return tlbi_fail(TLB_EINVAL, "grid size out of range");
+  if (d.max_batch < 1 || (long long)d.max_batch * d.n_theta * d.n_phi > (1LL << 28))
+    return tlbi_fail(TLB_EINVAL, "max_batch out of range");
+  for (int c = 0; c < 4; ++c)
+    if (!std::isfinite(d.in_shift[c]) || !finite_nonzero(d.in_scale[c]) ||
+        !finite_nonzero(d.out_scale[c]) || !std::isfinite(d.loss_weight[c]) ||
+        d.loss_weight[c] < 0.0f)
+      return tlbi_fail(TLB_EINVAL, "normalisation, output scale or loss weight invalid");
+  tlb_cnn* net = new (std::nothrow) tlb_cnn{};
+  if (!net) return tlbi_fail(TLB_ENOMEM, "host allocation failed");
+  net->d = d;
+  net->stream = static_cast<hipStream_t>(hip_stream);
+  net->H = d.n_theta;
+  net->W = d.n_phi;
+  net->B = d.max_batch;
+  net->HW = (long long)d.n_theta * d.n_phi;
+  const size_t nb = (size_t)net->B * net->HW;
+  const size_t P = TLB_CNN_PARAMS;
+  net->red_blocks = blocks_for((long long)nb, RED);
+  if (net->red_blocks < 1024) net->red_blocks = 1024;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  alloc((void**)&net->params, P * 4);
+  alloc((void**)&net->grad, P * 4);
+  alloc((void**)&net->mom, P * 4);
+  alloc((void**)&net->vel, P * 4);
+  for (int l = 0; l < NL; ++l) {
+    alloc((void**)&net->wf[l], frag_slots(l, false) * 2);
+    if (l > 0) alloc((void**)&net->wd[l], frag_slots(l, true) * 2);
+  }
+  for (int l = 0; l < 4; ++l) alloc((void**)&net->act[l], nb * WIDTH * 2);
+  alloc((void**)&net->z, nb * 16);
+  alloc((void**)&net->e4, nb * 16);
+  alloc((void**)&net->eA, nb * WIDTH * 2);
+  alloc((void**)&net->eB, nb * WIDTH * 2);
+  alloc((void**)&net->partial, (size_t)WG_MAX_BLOCKS * (32 * 9 * 32 + 32) * 4);
+  alloc((void**)&net->red, (size_t)net->red_blocks * 8 * 8);
+  alloc((void**)&net->scalars, 8 * 8);
+  alloc((void**)&net->Jrow, net->H * 4);
+  alloc((void**)&net->mbuf, net->HW * 16);
+  alloc((void**)&net->proj, net->H * 3 * 8);
+  if (e != hipSuccess) {
+    free_net(net);
+    return tlbi_fail(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  std::vector<float> J(net->H);
+  for (int q = 0; q < net->H; ++q) J[q] = (float)(d.R + d.r * std::cos(2.0 * M_PI * q / net->H));
+  std::vector<float> zero(P, 0.0f);
+  e = hipMemcpy(net->Jrow, J.data(), net->H * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(net->params, zero.data(), P * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(net->mom, zero.data(), P * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(net->vel, zero.data(), P * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_net(net);
+    return tlbi_fail(TLB_EHIP, std::string("upload: ") + hipGetErrorString(e));
+  }
+  std::vector<tlbi_launch> seq;
+  frags_seq(net, seq);
+  int32_t rc = run_all(seq, net->stream);
+  if (rc == TLB_OK && hipStreamSynchronize(net->stream) != hipSuccess)
+    rc = tlbi_fail(TLB_EHIP, "stream synchronisation failed");
+  if (rc != TLB_OK) {
+    free_net(net);
+    return rc;
+  }
+  *out = net;
+  return TLB_OK;
+}
+
+void tlb_cnn_destroy(tlb_cnn* net) {
+  if (!net) return;
+  (void)hipStreamSynchronize(net->stream);
+  free_net(net);
+}
+
+int32_t tlb_cnn_set_params(tlb_cnn* net, const float* host_params) {
+  if (!net || !host_params) return tlbi_fail(TLB_EINVAL, "network or params is NULL");
+  for (int i = 0; i < TLB_CNN_PARAMS; ++i)
+    if (!std::isfinite(host_params[i])) return tlbi_fail(TLB_EINVAL, "non-finite parameter");
+  LRN_HIP_CHECK(hipStreamSynchronize(net->stream));
+  std::vector<float> zero(TLB_CNN_PARAMS, 0.0f);
+  LRN_HIP_CHECK(hipMemcpy(net->params, host_params, TLB_CNN_PARAMS * 4, hipMemcpyHostToDevice));
+  LRN_HIP_CHECK(hipMemcpy(net->mom, zero.data(), TLB_CNN_PARAMS * 4, hipMemcpyHostToDevice));
+  LRN_HIP_CHECK(hipMemcpy(net->vel, zero.data(), TLB_CNN_PARAMS * 4, hipMemcpyHostToDevice));
+  std::vector<tlbi_launch> seq;
+  frags_seq(net, seq);
+  int32_t rc = run_all(seq, net->stream);
+  if (rc != TLB_OK) return rc;
+  LRN_HIP_CHECK(hipStreamSynchronize(net->stream));
+  return TLB_OK;
+}
+
+int32_t tlb_cnn_get_params(tlb_cnn* net, float* host_params) {
+  if (!net || !host_params) return tlbi_fail(TLB_EINVAL, "network or params is NULL");
+  LRN_HIP_CHECK(hipStreamSynchronize(net->stream));
+  LRN_HIP_CHECK(hipMemcpy(host_params, net->params, TLB_CNN_PARAMS * 4, hipMemcpyDeviceToHost));
+  return TLB_OK;
+}
+
+int32_t tlb_cnn_forward(tlb_cnn* net, const float* moments, const int32_t* idx, int32_t n,
+                        float* out) {
+  int32_t rc = check_batch(net, moments, n);
+  if (rc != TLB_OK) return rc;
+  if (!out) return tlbi_fail(TLB_EINVAL, "out is NULL");
+  std::vector<tlbi_launch> seq;
+  forward_seq(net, moments, idx, n, seq);
+  ScaleArgs sa{net->z, out, (long long)n * net->HW, {0, 0, 0, 0}};
+  for (int c = 0; c < 4; ++c) sa.s[c] = net->d.out_scale[c];
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&scale_kernel),
+                            dim3(blocks_for(sa.count, 256)), dim3(256), sa));
+  return run_all(seq, net->stream);
+}
+
+int32_t tlb_cnn_gradient(tlb_cnn* net, const float* moments, const float* targets,
+                         const int32_t* idx, int32_t n, double* loss, float* host_grad) {
+  int32_t rc = check_batch(net, moments, n);
+  if (rc != TLB_OK) return rc;
+  if (!targets) return tlbi_fail(TLB_EINVAL, "targets is NULL");
+  std::vector<tlbi_launch> seq;
+  forward_seq(net, moments, idx, n, seq);
+  backward_seq(net, moments, targets, idx, n, seq);
+  rc = run_all(seq, net->stream);
+  if (rc != TLB_OK) return rc;
+  LRN_HIP_CHECK(hipStreamSynchronize(net->stream));
+  if (loss) LRN_HIP_CHECK(hipMemcpy(loss, net->scalars, 8, hipMemcpyDeviceToHost));
+  if (host_grad)
+    LRN_HIP_CHECK(hipMemcpy(host_grad, net->grad, TLB_CNN_PARAMS * 4, hipMemcpyDeviceToHost));
+  return TLB_OK;
+}
+
+int32_t tlb_cnn_train_step(tlb_cnn* net, const float* moments, const float* targets,
+                           const int32_t* idx, int32_t n, const tlb_adam* adam, double* loss) {
+  int32_t rc = check_batch(net, moments, n);
+  if (rc != TLB_OK) return rc;
+  if (!targets || !adam) return tlbi_fail(TLB_EINVAL, "targets or adam is NULL");
+  if (adam->step < 1 || !(adam->lr >= 0.0f) || !(adam->beta1 >= 0.0f && adam->beta1 < 1.0f) ||
+      !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) || !(adam->eps > 0.0f))
+    return tlbi_fail(TLB_EINVAL, "Adam hyper-parameters out of range");
+  std::vector<tlbi_launch> seq;
+  forward_seq(net, moments, idx, n, seq);
+  backward_seq(net, moments, targets, idx, n, seq);
+  AdamArgs aa{};
+  aa.p = net->params;
+  aa.g = net->grad;
+  aa.m = net->mom;
+  aa.v = net->vel;
+  aa.count = TLB_CNN_PARAMS;
+  aa.lr = adam->lr;
+  aa.b1 = adam->beta1;
+  aa.b2 = adam->beta2;
+  aa.eps = adam->eps;
+  aa.c1 = (float)(1.0 - std::pow((double)adam->beta1, adam->step));
+  aa.c2 = (float)(1.0 - std::pow((double)adam->beta2, adam->step));
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&adam_kernel),
+                            dim3(blocks_for(TLB_CNN_PARAMS, 256)), dim3(256), aa));
+  frags_seq(net, seq);
+  rc = run_all(seq, net->stream);
+  if (rc != TLB_OK) return rc;
+  if (loss) {
+    LRN_HIP_CHECK(hipStreamSynchronize(net->stream));
+    LRN_HIP_CHECK(hipMemcpy(loss, net->scalars, 8, hipMemcpyDeviceToHost));
+  }
+  return TLB_OK;
+}
+
+int32_t tlb_learn_stats(const float* data, int64_t count, void* hip_stream, double out[8]) {
+  if (!data || !out || count < 1) return tlbi_fail(TLB_EINVAL, "data, out or count invalid");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int blocks = 512;
+  double* part = nullptr;
+  LRN_HIP_CHECK(hipMalloc(&part, (blocks * 8 + 8) * sizeof(double)));
+  StatArgs a{data, count, part};
+  std::vector<tlbi_launch> seq;
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&stats_kernel), dim3(blocks), dim3(RED), a));
+  SumArgs s{part, part + blocks * 8, blocks, 8, 1.0};
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(64), s));
+  int32_t rc = run_all(seq, stream);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (rc == TLB_OK && e == hipSuccess)
+    e = hipMemcpy(out, part + blocks * 8, 8 * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(part);
+  if (rc != TLB_OK) return rc;
+  if (e != hipSuccess) return tlbi_fail(TLB_EHIP, std::string("stats: ") + hipGetErrorString(e));
+  return TLB_OK;
+}
+
+int32_t tlb_restrict(const tlb_grid* fine, tlb_grid* coarse) {
+  int32_t rc = check_grid(fine, "fine grid");
+  if (rc == TLB_OK) rc = check_grid(coarse, "coarse grid");
+  if (rc != TLB_OK) return rc;
+  const tlb_params& pf = fine->p;
+  const tlb_params& pc = coarse->p;
+  if (pf.n_theta % pc.n_theta || pf.n_phi % pc.n_phi)
+    return tlbi_fail(TLB_EINVAL, "fine sizes are not multiples of the coarse ones");
+  const int k = pf.n_theta / pc.n_theta;
+  if (k != pf.n_phi / pc.n_phi || k < 2 || k % 2 || k > 32)
+    return tlbi_fail(TLB_EINVAL, "refinement factor must be the same even k in both angles, 2..32");
+  if (pf.r != pc.r || pf.R != pc.R || pf.precision != pc.precision ||
+      (pf.flags & TLB_FLAT) != (pc.flags & TLB_FLAT))
+    return tlbi_fail(TLB_EINVAL, "grids differ in radii, flat flag or precision");
+  std::vector<tlbi_launch> seq;
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    RestrictArgs<T> a{};
+    a.f = static_cast<const T*>(fine->f[0]);
+    a.phi = static_cast<const T*>(fine->phi[0]);
+    a.fc = static_cast<T*>(coarse->f[0]);
+    a.phic = static_cast<T*>(coarse->phi[0]);
+    a.area = fine->area;
+    a.Hf = pf.n_theta;
+    a.Wf = pf.n_phi;
+    a.Hc = pc.n_theta;
+    a.Wc = pc.n_phi;
+    a.k = k;
+    a.plane_f = (long long)pf.n_theta * pf.n_phi;
+    a.plane_c = (long long)pc.n_theta * pc.n_phi;
+    seq.push_back(make_launch(reinterpret_cast<const void*>(&restrict_kernel<T>),
+                              dim3(blocks_for(a.plane_c, 256)), dim3(256), a));
+  };
+  if (pf.precision == 64) go(double{}); else go(float{});
+  return run_all(seq, coarse->stream);
+}
+
+int32_t tlb_learn_pair(const tlb_grid* grid, const tlb_grid* truth, float* moments,
+                       float* targets) {
+  int32_t rc = check_grid(grid, "grid");
+  if (rc != TLB_OK) return rc;
+  if (!moments) return tlbi_fail(TLB_EINVAL, "moments is NULL");
+  if (truth) {
+    if (!targets) return tlbi_fail(TLB_EINVAL, "targets is NULL");
+    if (truth->p.n_theta != grid->p.n_theta || truth->p.n_phi != grid->p.n_phi ||
+        truth->p.precision != grid->p.precision)
+      return tlbi_fail(TLB_EINVAL, "truth grid differs in size or precision");
+  }
+  std::vector<tlbi_launch> seq;
+  if (grid->p.precision == 64)
+    pair_launch<double>(grid, truth, moments, targets, seq);
+  else
+    pair_launch<float>(grid, truth, moments, targets, seq);
+  return run_all(seq, grid->stream);
+}
+
+int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections) {
+  int32_t rc = check_grid(grid, "grid");
+  if (rc != TLB_OK) return rc;
+  if (!corrections) return tlbi_fail(TLB_EINVAL, "corrections is NULL");
+  double* proj = nullptr;
+  LRN_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&proj), grid->p.n_theta * 3 * sizeof(double)));
+  const float one[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+  std::vector<tlbi_launch> seq;
+  if (grid->p.precision == 64)
+    apply_launches<double>(grid, corrections, one, proj, seq);
+  else
+    apply_launches<float>(grid, corrections, one, proj, seq);
+  rc = run_all(seq, grid->stream);
+  const hipError_t e = hipStreamSynchronize(grid->stream);
+  (void)hipFree(proj);
+  if (rc == TLB_OK && e != hipSuccess)
+    rc = tlbi_fail(TLB_EHIP, std::string("apply: ") + hipGetErrorString(e));
+  return rc;
+}
+
+int32_t tlb_learned_step_n(tlb_grid* grid, tlb_cnn* net, int64_t n_steps) {
+  int32_t rc = check_grid(grid, "grid");
+  if (rc != TLB_OK) return rc;
+  if (!net) return tlbi_fail(TLB_EINVAL, "network is NULL");
+  if (n_steps < 0) return tlbi_fail(TLB_EINVAL, "n_steps < 0");
+  if (grid->p.n_theta != net->H || grid->p.n_phi != net->W)
+    return tlbi_fail(TLB_EINVAL, "grid size differs from the network's");
+  const bool use_graph = !(grid->p.flags & TLB_NO_GRAPH) && n_steps >= LEARN_GRAPH_CHUNK;
+  int64_t done = 0;
+  if (use_graph) {
+    if (!graph_matches(net, grid)) {
+      rc = build_learn_graph(grid, net);
+      if (rc != TLB_OK) return rc;
+    }
+    for (; done + LEARN_GRAPH_CHUNK <= n_steps; done += LEARN_GRAPH_CHUNK)
+      LRN_HIP_CHECK(hipGraphLaunch(net->chunk_exec, grid->stream));
+  }
+  if (done < n_steps) {
+    std::vector<tlbi_launch> seq;
+    learned_step_seq(grid, net, seq);
+    for (; done < n_steps; ++done) {
+      rc = run_all(seq, grid->stream);
+      if (rc != TLB_OK) return rc;
+    }
+  }
+  return TLB_OK;
+}
+
+}  // extern "C"

@@ -34,6 +34,7 @@
 #include <type_traits>
 
 #include "tlb.h"
+#include "tlb_internal.h"
 
 namespace {
 
@@ -56,18 +57,6 @@ int32_t fail(int32_t code, const std::string& msg) {
 // ------------------------------------------------------------------------------------------
 // velocity space (section II C)
 
-// Q = 4 Gauss-Hermite velocity set (eq. vmatrix) and weights w = (3 -/+ sqrt 6)/12, with the
-// irrational roots written out as literals so that every constant below folds at compile time.
-constexpr double SQRT6 = 2.449489742783178098197284074705891391966;
-constexpr double VOUT = 2.334414218338977239317512267210362194489;  // sqrt(3 + sqrt 6)
-constexpr double VIN = 0.7419637843027258576485135967263602248295;  // sqrt(3 - sqrt 6)
-
-__host__ __device__ constexpr double vel(int i) {
-  return i == 0 ? -VOUT : i == 1 ? -VIN : i == 2 ? VIN : VOUT;
-}
-__host__ __device__ constexpr double wgt(int i) {
-  return (i == 0 || i == 3) ? (3.0 - SQRT6) / 12.0 : (3.0 + SQRT6) / 12.0;
-}
 // probabilists' Hermite polynomials He_0..He_4, written out
 __host__ __device__ constexpr double hermite_e(int l, double x) {
   return l == 0 ? 1.0 : l == 1 ? x : l == 2 ? x * x - 1.0 : l == 3 ? x * x * x - 3.0 * x
@@ -79,17 +68,6 @@ __host__ __device__ constexpr double kh(int i, int m) {
                     hermite_e(2, vel(i)) * hermite_e(1, vel(m)) +
                     hermite_e(3, vel(i)) * hermite_e(2, vel(m)) / 2.0 +
                     hermite_e(4, vel(i)) * hermite_e(3, vel(m)) / 6.0);
-}
-
-template <int I>
-using ic = std::integral_constant<int, I>;
-// compile-time loop: fn(ic<B>{}), fn(ic<B+1>{}), ..., fn(ic<E-1>{})
-template <int B, int E, class F>
-__host__ __device__ __forceinline__ void static_for(F&& fn) {
-  if constexpr (B < E) {
-    fn(ic<B>{});
-    static_for<B + 1, E>(static_cast<F&&>(fn));
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -805,22 +783,6 @@ void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-struct tlb_grid {
-  tlb_params p;
-  void* f[3];
-  void* phi[3];
-  hipStream_t stream;
-  void* rows;       // RowCoef<T>[nt]
-  double* area;     // [nt]
-  double* partial;  // [3 * red_blocks + 3]
-  double* half_len; // [nt]: (R + r cos theta_{q+1/2}) dphi, the length of a theta-face
-  int red_blocks, rows_per_block;
-  size_t elem;
-  int ty;                     // tile height of the stage kernel (4, 8 or 16)
-  hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
-  bool chunk_tried;
-};
-
 struct tlb_batch {
   tlb_grid** grids;
   int n;
@@ -1204,6 +1166,24 @@ int32_t check_params(const tlb_params* p) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
+int32_t tlbi_fail(int32_t code, const std::string& msg) { return fail(code, msg); }
+
+void tlbi_stage_launch(const tlb_grid* g, int stage, tlbi_launch* out) {
+  out->grid = dim3(stage_blocks(g));
+  out->block = dim3(TX * g->ty);
+  if (g->p.precision == 64) {
+    static_assert(sizeof(StageArgs<double>) <= sizeof(out->args), "argument block");
+    out->fn = stage_fn<double>(g);
+    StageArgs<double> a = stage_args<double>(g, stage);
+    std::memcpy(out->args, &a, sizeof(a));
+  } else {
+    static_assert(sizeof(StageArgs<float>) <= sizeof(out->args), "argument block");
+    out->fn = stage_fn<float>(g);
+    StageArgs<float> a = stage_args<float>(g, stage);
+    std::memcpy(out->args, &a, sizeof(a));
+  }
+}
+
 extern "C" {
 
 const char* tlb_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,69 @@
+// tlb_internal.h -- declarations shared by the translation units of libtlb.so (the step
+// library tlb.hip and the learned-correction library learn.hip).  Not installed, not part of
+// the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <type_traits>
+
+#include "tlb.h"
+
+// A torus grid: the caller's state buffers, the stream, and the library's per-row tables.
+struct tlb_grid {
+  tlb_params p;
+  void* f[3];
+  void* phi[3];
+  hipStream_t stream;
+  void* rows;       // RowCoef<T>[nt]
+  double* area;     // [nt]: r J dtheta dphi, the area of a node of row q
+  double* partial;  // [3 * red_blocks + 3]
+  double* half_len; // [nt]: (R + r cos theta_{q+1/2}) dphi, the length of a theta-face
+  int red_blocks, rows_per_block;
+  size_t elem;
+  int ty;                     // tile height of the stage kernel (4, 8 or 16)
+  hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
+  bool chunk_tried;
+};
+
+// Records `msg` as the thread's last error and returns `code`.
+int32_t tlbi_fail(int32_t code, const std::string& msg);
+
+// One kernel launch with a single by-value argument block, replayable as a graph node.
+struct tlbi_launch {
+  const void* fn;
+  dim3 grid, block;
+  alignas(16) unsigned char args[512];
+};
+
+// The launch of Runge-Kutta stage `stage` (1..3) of one time step of grid g.
+void tlbi_stage_launch(const tlb_grid* g, int stage, tlbi_launch* out);
+
+namespace {
+
+// Q = 4 Gauss-Hermite velocity set (eq. vmatrix) and weights w = (3 -/+ sqrt 6)/12, with the
+// irrational roots written out as literals so that every constant below folds at compile time.
+constexpr double SQRT6 = 2.449489742783178098197284074705891391966;
+constexpr double VOUT = 2.334414218338977239317512267210362194489;  // sqrt(3 + sqrt 6)
+constexpr double VIN = 0.7419637843027258576485135967263602248295;  // sqrt(3 - sqrt 6)
+
+__host__ __device__ constexpr double vel(int i) {
+  return i == 0 ? -VOUT : i == 1 ? -VIN : i == 2 ? VIN : VOUT;
+}
+__host__ __device__ constexpr double wgt(int i) {
+  return (i == 0 || i == 3) ? (3.0 - SQRT6) / 12.0 : (3.0 + SQRT6) / 12.0;
+}
+
+template <int I>
+using ic = std::integral_constant<int, I>;
+// compile-time loop: fn(ic<B>{}), fn(ic<B+1>{}), ..., fn(ic<E-1>{})
+template <int B, int E, class F>
+__host__ __device__ __forceinline__ void static_for(F&& fn) {
+  if constexpr (B < E) {
+    fn(ic<B>{});
+    static_for<B + 1, E>(static_cast<F&&>(fn));
+  }
+}
+
+}  // namespace

@@ -194,3 +194,40 @@ def ensemble_workload(n=64, seed=4):
         p = params_three_cells(1.0, R, nt, 2 * nt, A=0.5, M=2.5e-3, tau=0.6, dt=1.0)
         out.append(p.with_(dt=stable_dt(p)))
     return out
+
+
+# -- the learned coarse-step correction -------------------------------------------------------------
+
+CNN_ARCH = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 4))   # (inputs, outputs) per layer
+
+
+def cnn_init_params(seed, last_gain=0.1):
+    """Seeded He-normal initial weights (std sqrt(2 / (9 c_in))), zero biases, the last layer
+    scaled by last_gain; flat FP32 vector, layer by layer W[c_out][9][c_in] then b[c_out]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (ci, co) in enumerate(CNN_ARCH):
+        std = math.sqrt(2.0 / (9 * ci)) * (last_gain if l == len(CNN_ARCH) - 1 else 1.0)
+        parts += [rng.normal(0.0, std, size=co * 9 * ci), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def learn_samples(seed, n, n_theta, n_phi):
+    """Seeded synthetic moment samples (phi, n, u_theta, u_phi) and targets, float32
+    [n, n_theta, n_phi, 4] each, with the magnitudes of coarse spinodal states and of their
+    per-step corrections."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n_theta, n_phi)
+    m = np.stack([rng.uniform(-1, 1, shape), 1 + 0.02 * rng.normal(size=shape),
+                  0.01 * rng.normal(size=shape), 0.01 * rng.normal(size=shape)], -1)
+    y = rng.normal(size=shape + (4,)) * np.array([1e-3, 1e-6, 1e-5, 1e-5])
+    return m.astype(np.float32), y.astype(np.float32)
+
+
+def random_populations(n_theta, n_phi, seed):
+    """Seeded positive populations f[16, n_theta, n_phi] (each in (0.5, 1.5)/16) and
+    phi in (-1, 1), float64: states away from any equilibrium for operator tests."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.5, 1.5, size=(16, n_theta, n_phi)) / 16.0
+    phi = rng.uniform(-1, 1, size=(n_theta, n_phi))
+    return f, phi

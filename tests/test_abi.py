@@ -13,9 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "tlb.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tlb_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(tlb_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -96,3 +100,46 @@ def test_binding_refuses_to_run_without_gpu():
     from paper_1904_10070_amd import TorusGrid, inputs
     with pytest.raises(RuntimeError):
         TorusGrid(inputs.drop_workload())
+
+
+def cnn_desc(**kw):
+    d = binding.CnnDesc(1.0, 2.5, 16, 40, 4, 0)
+    for c in range(4):
+        d.in_scale[c] = 1.0
+        d.out_scale[c] = 1.0
+        d.loss_weight[c] = 1.0
+    for k, v in kw.items():
+        if isinstance(v, tuple):
+            arr = getattr(d, k)
+            for c in range(4):
+                arr[c] = v[c]
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=0.5), dict(n_theta=0), dict(max_batch=0),
+                                 dict(in_scale=(1.0, 0.0, 1.0, 1.0)),
+                                 dict(out_scale=(1.0, 1.0, float("nan"), 1.0)),
+                                 dict(loss_weight=(1.0, -1.0, 1.0, 1.0))])
+def test_cnn_create_rejects_bad_descriptors(lib, bad):
+    h = ctypes.c_void_p()
+    d = cnn_desc(**bad)
+    assert lib.tlb_cnn_create(ctypes.byref(d), None, ctypes.byref(h)) == binding.TLB_EINVAL
+    assert h.value is None and lib.tlb_last_error()
+
+
+def test_learning_entry_points_reject_null(lib):
+    assert lib.tlb_cnn_create(None, None, None) == binding.TLB_EINVAL
+    assert lib.tlb_cnn_set_params(None, None) == binding.TLB_EINVAL
+    assert lib.tlb_cnn_get_params(None, None) == binding.TLB_EINVAL
+    assert lib.tlb_cnn_forward(None, None, None, 1, None) == binding.TLB_EINVAL
+    assert lib.tlb_cnn_gradient(None, None, None, None, 1, None, None) == binding.TLB_EINVAL
+    assert lib.tlb_cnn_train_step(None, None, None, None, 1, None, None) == binding.TLB_EINVAL
+    out = (ctypes.c_double * 8)()
+    assert lib.tlb_learn_stats(None, 4, None, out) == binding.TLB_EINVAL
+    assert lib.tlb_restrict(None, None) == binding.TLB_EINVAL
+    assert lib.tlb_learn_pair(None, None, None, None) == binding.TLB_EINVAL
+    assert lib.tlb_apply_correction(None, None) == binding.TLB_EINVAL
+    assert lib.tlb_learned_step_n(None, None, 1) == binding.TLB_EINVAL
+    lib.tlb_cnn_destroy(None)

@@ -9,6 +9,12 @@ import numpy as np
 import pytest
 
 from oracle import cnn_ref as C
+from paper_1904_10070_amd import inputs
+
+
+def test_architecture_tables_agree():
+    assert tuple(inputs.CNN_ARCH) == tuple(C.ARCH)
+    assert C.param_count() == 30660 == len(inputs.cnn_init_params(0))
 
 
 def test_bf16_rounding_matches_torch():
@@ -76,7 +82,7 @@ def small_problem(seed, N=2, H=5, W=6):
     y = rng.normal(size=(N, H, W, 4)) * np.array([1e-3, 1e-5, 1e-4, 1e-4])
     geo = dict(r=1.0, R=2.5, shift=[0.0, 1.0, 0.0, 0.0], scale=[1.0, 20.0, 100.0, 100.0],
                out_scale=[1e-3, 1e-5, 1e-4, 1e-4], loss_weight=[2.0, 1.0, 0.5, 0.5])
-    params = C.init_params(seed, last_gain=1.0).astype(np.float64)
+    params = inputs.cnn_init_params(seed, last_gain=1.0).astype(np.float64)
     params += 0.01 * rng.normal(size=params.shape)        # nonzero biases
     return params, m, y, geo
 
