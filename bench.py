@@ -6,8 +6,10 @@ force and connection terms, Cahn-Hilliard) over the whole grid, with the state r
 
 Headline workload: spinodal coarsening on a 512 x 1280 torus (r = 1, R = 2.5, tau = 0.6,
 M = 2.5e-3, phi ~ U[-0.1, 0.1] from seed 7, n = 1, u = 0), populations stored and stepped in
-FP32.  The same line also carries the FP64 rate on that workload and the FP32 rate on a
-2048 x 5120 grid whose working set (2.1 GB) is far larger than the 256 MB last-level cache.
+FP32.  The same line also carries the FP64 rate on that workload, the FP32 rate on a
+2048 x 5120 grid whose working set (2.1 GB) is far larger than the 256 MB last-level cache, the
+batched ensemble of 64 tori against separate runs, and the learned coarse step's speedup over
+the fine FP32 step with its coarsening-length error against the fine solver.
 
 Roofline: the stage kernel is HBM-bound.  Algorithmic traffic per node and time step is 136
 values (stage 1 reads y^n and writes y1: 16 + 16 populations, 1 + 1 phi; stages 2 and 3 read
@@ -99,6 +101,56 @@ def ensemble_leg(steps, warmup):
             "steps": steps}
 
 
+def learned_leg(t_fine_step, steps=2000, seed=7, t_start=20.0, t_end=28.0, every_t=2.0):
+    """The learned coarse step (128 x 320, 4x time step, weights trained by train_coarse.py)
+    on a held-out seed: the fine FP32 solver runs the spinodal workload to t_start, hands its
+    state to a learned and a plain coarse grid, and judges both up to t_end by the coarsening
+    length L_d of the restricted fine state.  Speed: GPU time per unit of simulated time of the
+    learned and plain coarse steps against the fine FP32 step."""
+    import torch
+    from paper_1904_10070_amd import TorusGrid, inputs, learn as L, train_coarse
+    from paper_1904_10070_amd.binding import learned_step
+    params, meta = train_coarse.load(0.6)
+    net = train_coarse.network_from(meta, params)
+    pf = inputs.spinodal_workload(0.6)
+    pc = L.coarse_params(pf)
+    rows = L.evaluate(pf, net, seed, t_start, t_end, every_t, progress=None)
+    err = [abs(r["L_learned"] - r["L_judge"]) / r["L_judge"] for r in rows]
+    err_p = [abs(r["L_plain"] - r["L_judge"]) / r["L_judge"] for r in rows]
+
+    def per_step(stepper):
+        g = TorusGrid(pc, precision=32)
+        g.set_state(inputs.spinodal_phi(pc, seed=seed), *inputs.rest_moments(pc.n_theta, pc.n_phi))
+        stepper(g, 64)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(g.stream)
+        stepper(g, steps)
+        stop.record(g.stream)
+        torch.cuda.synchronize()
+        g.close()
+        return start.elapsed_time(stop) * 1e-3 / steps
+
+    t_learned = per_step(lambda g, n: learned_step(g, net, n))
+    t_plain = per_step(lambda g, n: g.step(n))
+    fine_per_t = t_fine_step / pf.dt
+    return {"workload": f"spinodal {pf.n_theta}x{pf.n_phi} (tau=0.6) -> learned coarse "
+                        f"{pc.n_theta}x{pc.n_phi}, dt x{round(pc.dt / pf.dt)}; hand-over at "
+                        f"t={t_start:g} from held-out seed {seed}, judged to t={t_end:g}",
+            "L_error_max": max(err), "L_error_max_plain_coarse": max(err_p),
+            "phi_l2_end": rows[-1]["phi_l2_learned"], "phi_l2_end_plain_coarse": rows[-1]["phi_l2_plain"],
+            "speedup_vs_fine_fp32": fine_per_t / (t_learned / pc.dt),
+            "speedup_plain_coarse": fine_per_t / (t_plain / pc.dt),
+            "ms_per_learned_step": t_learned * 1e3, "ms_per_plain_coarse_step": t_plain * 1e3,
+            "ms_per_fine_step": t_fine_step * 1e3, "steps_timed": steps,
+            "rows": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()}
+                     for r in rows],
+            "training": {"samples": meta["samples"], "data_s": meta["data_seconds"],
+                         "train_s": meta["train_seconds"],
+                         "validation_seed": meta["validation"]["seed"],
+                         "validation_L_error": meta["validation"]["largest_L_error"]}}
+
+
 def measured_traffic(key):
     """HBM bytes per launch of the stage kernel from the committed counter summary
     (profiles/stage_kernel_traffic.json), or None if the kernel source changed since."""
@@ -161,7 +213,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
     ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64",
-                                       "ensemble32"],
+                                       "ensemble32", "learned32"],
                     help="time a single workload/precision (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
@@ -193,6 +245,10 @@ def main():
     if args.only == "ensemble32":
         print(json.dumps(ensemble_leg(args.steps, args.warmup)))
         return
+    if args.only == "learned32":
+        d = gpu_leg(inputs.spinodal_workload(0.6), 32, args.steps, args.warmup)
+        print(json.dumps(learned_leg(d["t_step"], steps=args.steps)))
+        return
     if args.only:
         wl, prec = args.only[:-2], int(args.only[-2:])
         p = inputs.spinodal_workload(0.6) if wl == "spinodal" else inputs.roofline_workload()
@@ -207,7 +263,7 @@ def main():
     p = inputs.spinodal_workload(0.6)
     head = gpu_leg(p, 32, args.steps, args.warmup)
     out = {
-        "metric": "node-updates/s & % HBM peak, FP32 vs FP64",
+        "metric": "node-updates/s & % HBM peak, FP32 vs FP64; batched + learned-coarse speedup at err",
         "value": head["nups"],
         "unit": "node-updates/s",
         "n_gpus": 1,
@@ -248,6 +304,7 @@ def main():
         out["drop64x160_fp64"] = {"value": d["nups"], "unit": "node-updates/s",
                                   "ms_per_step": d["t_step"] * 1e3, "steps": 2000}
         out["ensemble64_fp32"] = ensemble_leg(max(10, args.steps // 10), 5)
+        out["learned_coarse_fp32"] = learned_leg(head["t_step"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -23,7 +23,8 @@
  *             sums over blocks in FP64).
  *   correct   dphi and dn lose their area-weighted means (so mass and the J-weighted sum of
  *             phi are unchanged), then f += f_eq(n + dn, u + du) - f_eq(n, u) with the
- *             equilibrium of eq. feq, and phi += dphi.
+ *             equilibrium of eq. feq, and phi += dphi.  In the learned step, corrections
+ *             outside the descriptor's apply_mask are zero.
  *   train     loss L = sum_c w_c (z_c - y_c / out_scale_c)^2 / (4 N n_theta n_phi) over a
  *             batch of N samples, y the target corrections; its gradient with respect to the
  *             FP32 weights (through the bfloat16 rounding unchanged); Adam (Kingma & Ba).
@@ -59,13 +60,13 @@ typedef struct tlb_cnn tlb_cnn;
 
 /* Descriptor of a network: the torus and grid it runs on (n_theta x n_phi nodes, radii r < R
  * for the J input), the largest batch of samples a call may pass (sizes the workspace:
- * about 330 bytes per node and sample), the input normalisation, the output scale and the
- * loss weights.                                                                            */
+ * about 420 bytes per node and sample), which corrections the learned step applies, the
+ * input normalisation, the output scale and the loss weights.                             */
 typedef struct {
   double r, R;
   int32_t n_theta, n_phi;
   int32_t max_batch;
-  int32_t reserved; /* 0 */
+  uint32_t apply_mask; /* bit c set: correction c is applied (0 = all four)             */
   float in_shift[4], in_scale[4];
   float out_scale[4];
   float loss_weight[4];

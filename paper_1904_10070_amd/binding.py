@@ -54,7 +54,7 @@ class Buffers(ctypes.Structure):
 class CnnDesc(ctypes.Structure):
     _fields_ = [("r", ctypes.c_double), ("R", ctypes.c_double),
                 ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("apply_mask", ctypes.c_uint32),
                 ("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
                 ("out_scale", ctypes.c_float * 4), ("loss_weight", ctypes.c_float * 4)]
 
@@ -317,10 +317,11 @@ class CoarseCNN:
     """The periodic five-layer 3x3 network of tlb_learn.h, trained and run by libtlb's kernels.
 
     r, R, n_theta, n_phi: the torus and grid it runs on; max_batch: largest batch of samples;
-    in_shift / in_scale (4 each), out_scale (4), loss_weight (4): as in tlb_cnn_desc."""
+    in_shift / in_scale (4 each), out_scale (4), loss_weight (4), apply_mask: as in
+    tlb_cnn_desc."""
 
     def __init__(self, r, R, n_theta, n_phi, max_batch, in_shift, in_scale, out_scale,
-                 loss_weight=(1.0, 1.0, 1.0, 1.0), stream=None):
+                 loss_weight=(1.0, 1.0, 1.0, 1.0), apply_mask=0, stream=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -329,7 +330,7 @@ class CoarseCNN:
         self.shape = (int(n_theta), int(n_phi))
         self.max_batch = int(max_batch)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        d = CnnDesc(float(r), float(R), int(n_theta), int(n_phi), int(max_batch), 0)
+        d = CnnDesc(float(r), float(R), int(n_theta), int(n_phi), int(max_batch), int(apply_mask))
         for name, vals in (("in_shift", in_shift), ("in_scale", in_scale),
                            ("out_scale", out_scale), ("loss_weight", loss_weight)):
             arr = getattr(d, name)

@@ -937,10 +937,13 @@ void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) 
   else
     pair_launch<float>(g, nullptr, net->mbuf, nullptr, seq);
   forward_seq(net, net->mbuf, nullptr, 1, seq);
+  float scale[4];
+  for (int c = 0; c < 4; ++c)
+    scale[c] = (net->d.apply_mask == 0 || ((net->d.apply_mask >> c) & 1u)) ? net->d.out_scale[c] : 0.0f;
   if (g->p.precision == 64)
-    apply_launches<double>(g, net->z, net->d.out_scale, net->proj, seq);
+    apply_launches<double>(g, net->z, scale, net->proj, seq);
   else
-    apply_launches<float>(g, net->z, net->d.out_scale, net->proj, seq);
+    apply_launches<float>(g, net->z, scale, net->proj, seq);
 }
 
 void drop_learn_graph(tlb_cnn* net) {
@@ -1035,6 +1038,7 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
         !finite_nonzero(d.out_scale[c]) || !std::isfinite(d.loss_weight[c]) ||
         d.loss_weight[c] < 0.0f)
       return tlbi_fail(TLB_EINVAL, "normalisation, output scale or loss weight invalid");
+  if (d.apply_mask > 15u) return tlbi_fail(TLB_EINVAL, "apply_mask has bits above the four outputs");
   tlb_cnn* net = new (std::nothrow) tlb_cnn{};
   if (!net) return tlbi_fail(TLB_ENOMEM, "host allocation failed");
   net->d = d;

@@ -121,7 +121,7 @@ def cnn_desc(**kw):
 @pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=0.5), dict(n_theta=0), dict(max_batch=0),
                                  dict(in_scale=(1.0, 0.0, 1.0, 1.0)),
                                  dict(out_scale=(1.0, 1.0, float("nan"), 1.0)),
-                                 dict(loss_weight=(1.0, -1.0, 1.0, 1.0))])
+                                 dict(loss_weight=(1.0, -1.0, 1.0, 1.0)), dict(apply_mask=16)])
 def test_cnn_create_rejects_bad_descriptors(lib, bad):
     h = ctypes.c_void_p()
     d = cnn_desc(**bad)

@@ -177,3 +177,4 @@ def test_correction_moment_identities():
     assert abs(np.sum(J * phi2) - np.sum(J * phi)) < 1e-13 * np.sum(J)
     f3, phi3 = C.apply_correction(f, phi, np.zeros((H, W, 4)), r, R)
     assert np.allclose(f3, f, rtol=1e-15, atol=0) and np.array_equal(phi3, phi)
+
