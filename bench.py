@@ -119,7 +119,7 @@ def learned_leg(t_fine_step, steps=2000, seed=7, t_start=20.0, t_end=28.0, every
     err_p = [abs(r["L_plain"] - r["L_judge"]) / r["L_judge"] for r in rows]
 
     def per_step(stepper):
-        g = TorusGrid(pc, precision=32)
+        g = L.coarse_grid(pc, precision=32)
         g.set_state(inputs.spinodal_phi(pc, seed=seed), *inputs.rest_moments(pc.n_theta, pc.n_phi))
         stepper(g, 64)
         torch.cuda.synchronize()
@@ -149,6 +149,67 @@ def learned_leg(t_fine_step, steps=2000, seed=7, t_start=20.0, t_end=28.0, every
                          "train_s": meta["train_seconds"],
                          "validation_seed": meta["validation"]["seed"],
                          "validation_L_error": meta["validation"]["largest_L_error"]}}
+
+
+def learned_step_timing(steps=2000):
+    """GPU time per learned and per plain coarse step on the 128 x 320 grid (profiling runs)."""
+    import torch
+    from paper_1904_10070_amd import TorusGrid, inputs, learn as L, train_coarse
+    from paper_1904_10070_amd.binding import learned_step
+    params, meta = train_coarse.load(0.6)
+    net = train_coarse.network_from(meta, params)
+    pc = L.coarse_params(inputs.spinodal_workload(0.6))
+    out = {}
+    for name, stepper in (("learned", lambda g, n: learned_step(g, net, n)),
+                          ("plain", lambda g, n: g.step(n))):
+        g = L.coarse_grid(pc, precision=32)
+        out["tile_rows"] = g.tile_rows
+        g.set_state(inputs.spinodal_phi(pc, seed=7), *inputs.rest_moments(pc.n_theta, pc.n_phi))
+        stepper(g, 64)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(g.stream)
+        stepper(g, steps)
+        stop.record(g.stream)
+        torch.cuda.synchronize()
+        out[f"ms_per_{name}_step"] = start.elapsed_time(stop) / steps
+        g.close()
+    return out
+
+
+# algorithmic multiply-add work of the network per node: sum over layers of 2 * 9 * c_in * c_out
+# (forward), the same again for the weight gradient, and for the input gradient of layers 1..4
+CNN_ARCH = ((6, 32), (32, 32), (32, 32), (32, 32), (32, 4))
+CNN_FWD_FLOP = sum(2 * 9 * ci * co for ci, co in CNN_ARCH)
+CNN_TRAIN_FLOP = 2 * CNN_FWD_FLOP + sum(2 * 9 * ci * co for ci, co in CNN_ARCH[1:])
+
+
+def training_timing(iters=200, batch=16):
+    """Training steps of the network on seeded synthetic pairs of the 128 x 320 coarse grid:
+    time per step and the algorithmic bf16 matrix-core rate it implies."""
+    import torch
+    from paper_1904_10070_amd import inputs
+    from paper_1904_10070_amd.binding import CoarseCNN
+    H, W, S = 128, 320, 64
+    m, y = inputs.learn_samples(3, S, H, W)
+    m, y = torch.tensor(m, device="cuda"), torch.tensor(y, device="cuda")
+    net = CoarseCNN(1.0, 2.5, H, W, batch, (0.0, 1.0, 0.0, 0.0), (1.0, 50.0, 100.0, 100.0),
+                    (1e-3, 1e-6, 1e-5, 1e-5))
+    net.set_params(inputs.cnn_init_params(0))
+    rng = __import__("numpy").random.default_rng(0)
+    idx = [rng.choice(S, size=batch, replace=False) for _ in range(iters + 10)]
+    for it in range(10):
+        net.train_step(m, y, idx[it], it + 1, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        net.train_step(m, y, idx[10 + it], 11 + it, 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    flop = CNN_TRAIN_FLOP * batch * H * W
+    return {"ms_per_train_step": dt * 1e3, "batch": batch, "grid": f"{H}x{W}",
+            "tflops": flop / dt / 1e12, "bf16_peak_tflops": 2500.0,
+            "frac": flop / dt / 1e12 / 2500.0}
 
 
 def measured_traffic(key):
@@ -213,7 +274,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
     ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64",
-                                       "ensemble32", "learned32"],
+                                       "ensemble32", "learned32", "learnedstep32", "train32"],
                     help="time a single workload/precision (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
@@ -244,6 +305,12 @@ def main():
         return
     if args.only == "ensemble32":
         print(json.dumps(ensemble_leg(args.steps, args.warmup)))
+        return
+    if args.only == "learnedstep32":
+        print(json.dumps(learned_step_timing(args.steps)))
+        return
+    if args.only == "train32":
+        print(json.dumps(training_timing(args.steps)))
         return
     if args.only == "learned32":
         d = gpu_leg(inputs.spinodal_workload(0.6), 32, args.steps, args.warmup)

@@ -119,20 +119,62 @@ struct ConvArgs {
   void* out;             // bf16 [n][H][W][32], or float [n][H][W][4] (EPI_OUT)
   Features F;
   int n, H, W, xt, tiles;  // xt = ceil(W / 16) node groups per row; tiles = n H xt
+  // EPI_OUT, optional (proj != NULL): per-block sums of area-weighted corrections,
+  // proj[block] = (sum a z0 s0, sum a z1 s1, sum a), area[H] the node area of each row
+  double* proj;
+  const double* area;
+  float s0, s1;
 };
 
 constexpr int CONV_THREADS = 256;
 constexpr int CONV_WAVES = CONV_THREADS / 64;
 
+// The node operand of one tile: for each 32-long chunk c, this lane's 8 products -- tap c
+// with channels 8g..8g+7 (32-channel input), or tap 4c+g with all 8 channels (8-channel
+// input; taps 9..11 are zero padding).
+template <int IN, int KC>
+__device__ __forceinline__ void load_node_operand(const ConvArgs& a, int t, int px, int g,
+                                                  bf16x8 (&bf)[KC]) {
+  const int xb = t % a.xt;
+  const int rest = t / a.xt;
+  const int y = rest % a.H, n = rest / a.H;
+  const int x = xb * 16 + px;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const int tap = IN == IN_BF32 ? c : 4 * c + g;
+    bf[c] = zero_frag();
+    if (tap < 9) {
+      const int yy = wrap(y + tap / 3 - 1, a.H);
+      const int xx = wrap(x + tap % 3 - 1, a.W);
+      const size_t pix = ((size_t)n * a.H + yy) * a.W + xx;
+      if constexpr (IN == IN_BF32) {
+        bf[c] = static_cast<const bf16x8*>(a.in)[pix * 4 + g];
+      } else if constexpr (IN == IN_BF8) {
+        bf[c] = static_cast<const bf16x8*>(a.in)[pix];
+      } else {
+        const int smp = a.idx ? a.idx[n] : n;
+        const size_t mp = ((size_t)smp * a.H + yy) * a.W + xx;
+        bf[c] = features(a.F, static_cast<const float4*>(a.in)[mp], yy);
+      }
+    }
+  }
+}
+
 template <int IN, int COB, int EPI>
 __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
   constexpr int KC = IN == IN_BF32 ? 9 : 3;  // 32-long product chunks
   __shared__ bf16x8 sw[KC * COB * 64];
-  for (int i = threadIdx.x; i < KC * COB * 64; i += CONV_THREADS) sw[i] = a.w[i];
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
-  for (int t = blockIdx.x * CONV_WAVES + wave; t < a.tiles; t += gridDim.x * CONV_WAVES) {
+  const int stride = gridDim.x * CONV_WAVES;
+  int t = blockIdx.x * CONV_WAVES + wave;
+  // the first tile's node operand is in flight while the weights are staged
+  bf16x8 bf[KC];
+  if (t < a.tiles) load_node_operand<IN, KC>(a, t, px, g, bf);
+  for (int i = threadIdx.x; i < KC * COB * 64; i += CONV_THREADS) sw[i] = a.w[i];
+  __syncthreads();
+  double ps0 = 0.0, ps1 = 0.0, pa = 0.0;  // EPI_OUT projection sums of this lane
+  for (; t < a.tiles; t += stride) {
     const int xb = t % a.xt;
     const int rest = t / a.xt;
     const int y = rest % a.H, n = rest / a.H;
@@ -141,30 +183,12 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
 #pragma unroll
     for (int b = 0; b < COB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      // this lane's 8 products of chunk c: tap c with channels 8g..8g+7 (32-channel input),
-      // or tap 4c+g with all 8 channels (8-channel input; taps 9..11 are zero padding)
-      const int tap = IN == IN_BF32 ? c : 4 * c + g;
-      bf16x8 bfrag = zero_frag();
-      if (tap < 9) {
-        const int yy = wrap(y + tap / 3 - 1, a.H);
-        const int xx = wrap(x + tap % 3 - 1, a.W);
-        const size_t pix = ((size_t)n * a.H + yy) * a.W + xx;
-        if constexpr (IN == IN_BF32) {
-          bfrag = static_cast<const bf16x8*>(a.in)[pix * 4 + g];
-        } else if constexpr (IN == IN_BF8) {
-          bfrag = static_cast<const bf16x8*>(a.in)[pix];
-        } else {
-          const int smp = a.idx ? a.idx[n] : n;
-          const size_t mp = ((size_t)smp * a.H + yy) * a.W + xx;
-          bfrag = features(a.F, static_cast<const float4*>(a.in)[mp], yy);
-        }
-      }
+    for (int c = 0; c < KC; ++c)
 #pragma unroll
       for (int b = 0; b < COB; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sw[(c * COB + b) * 64 + lane], bfrag,
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sw[(c * COB + b) * 64 + lane], bf[c],
                                                          acc[b], 0, 0, 0);
-    }
+    if (t + stride < a.tiles) load_node_operand<IN, KC>(a, t + stride, px, g, bf);
     if (x >= a.W) continue;
     // lane holds node x, output channels 16 b + 4 g + i
     const size_t opix = ((size_t)n * a.H + y) * a.W + x;
@@ -176,6 +200,12 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
         o.z = acc[0][2] + a.bias[2];
         o.w = acc[0][3] + a.bias[3];
         static_cast<float4*>(a.out)[opix] = o;
+        if (a.proj) {
+          const double ar = a.area[y];
+          ps0 += ar * (double)(o.x * a.s0);
+          ps1 += ar * (double)(o.y * a.s1);
+          pa += ar;
+        }
       }
     } else {
 #pragma unroll
@@ -196,6 +226,28 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
         st.x = (unsigned)to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
         st.y = (unsigned)to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
         *reinterpret_cast<uint2*>(static_cast<u16*>(a.out) + opix * 32 + co) = st;
+      }
+    }
+  }
+  if constexpr (EPI == EPI_OUT) {
+    if (a.proj) {  // uniform: every thread takes part in the fixed-order block sums
+      __shared__ double sh[CONV_WAVES][3];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        ps0 += __shfl_xor(ps0, d, 64);
+        ps1 += __shfl_xor(ps1, d, 64);
+        pa += __shfl_xor(pa, d, 64);
+      }
+      if (lane == 0) {
+        sh[wave][0] = ps0;
+        sh[wave][1] = ps1;
+        sh[wave][2] = pa;
+      }
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        double v = 0.0;
+        for (int w = 0; w < CONV_WAVES; ++w) v += sh[w][threadIdx.x];
+        a.proj[3 * blockIdx.x + threadIdx.x] = v;
       }
     }
   }
@@ -321,21 +373,35 @@ struct GradArgs {
   double scale;
 };
 
+// 64 parameters per block; each of the four wavefronts sums every fourth partial block of
+// them, and the four sums are added in a fixed order
+constexpr int GR_PARAMS = 64;
+
 __global__ __launch_bounds__(256) void grad_reduce_kernel(GradArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double part[4][GR_PARAMS];
+  const int lane = threadIdx.x & 63, quarter = threadIdx.x >> 6;
+  const int p = blockIdx.x * GR_PARAMS + lane;
   const int nw = a.cout * 9 * a.cin;
-  if (p >= nw + a.cout) return;
-  int src;
-  if (p < nw) {
-    const int co = p / (9 * a.cin), rem = p % (9 * a.cin);
-    src = (co * 9 + rem / a.cin) * a.cis + rem % a.cin;
-  } else {
-    src = a.cos_s * 9 * a.cis + (p - nw);
+  const bool valid = p < nw + a.cout;
+  int src = 0;
+  if (valid) {
+    if (p < nw) {
+      const int co = p / (9 * a.cin), rem = p % (9 * a.cin);
+      src = (co * 9 + rem / a.cin) * a.cis + rem % a.cin;
+    } else {
+      src = a.cos_s * 9 * a.cis + (p - nw);
+    }
   }
   const size_t stride = (size_t)a.cos_s * 9 * a.cis + a.cos_s;
   double s = 0.0;
-  for (int b = 0; b < a.blocks; ++b) s += (double)a.partial[b * stride + src];
-  a.grad[p] = (float)(s * a.scale);
+  if (valid) {
+#pragma unroll 8
+    for (int b = quarter; b < a.blocks; b += 4) s += (double)a.partial[b * stride + src];
+  }
+  part[quarter][lane] = s;
+  __syncthreads();
+  if (quarter == 0 && valid)
+    a.grad[p] = (float)(((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * a.scale);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -400,12 +466,14 @@ struct SumArgs {
   double scale;
 };
 
-__global__ __launch_bounds__(64) void sum_partials_kernel(SumArgs a) {
-  const int c = threadIdx.x;
-  if (c >= a.width) return;
-  double s = 0.0;
-  for (int b = 0; b < a.blocks; ++b) s += a.partial[(size_t)b * a.width + c];
-  a.out[c] = s * a.scale;
+__global__ __launch_bounds__(RED) void sum_partials_kernel(SumArgs a) {
+  __shared__ double sh[RED / 64];
+  for (int c = 0; c < a.width; ++c) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < a.blocks; b += RED) s += a.partial[(size_t)b * a.width + c];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) a.out[c] = t * a.scale;
+  }
 }
 
 // network output times the output scale
@@ -555,8 +623,8 @@ struct ApplyArgs {
   T* f;
   T* phi;
   const float* d;           // corrections [HW][4], times scale
-  const double* partial;    // [H][3]
-  int H;
+  const double* partial;    // [nparts][3]: sum a dphi, sum a dn, sum a
+  int nparts;
   long long plane;
   float scale[4];
 };
@@ -571,13 +639,23 @@ __device__ __forceinline__ T feq_k(int i, int j, T n, T ut, T up) {
 template <typename T>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs<T> a) {
   __shared__ double mean[2];
-  if (threadIdx.x < 2) {
-    double s = 0.0, ar = 0.0;
-    for (int q = 0; q < a.H; ++q) {
-      s += a.partial[3 * q + threadIdx.x];
+  if (threadIdx.x < 64) {
+    double s0 = 0.0, s1 = 0.0, ar = 0.0;
+    for (int q = threadIdx.x; q < a.nparts; q += 64) {
+      s0 += a.partial[3 * q + 0];
+      s1 += a.partial[3 * q + 1];
       ar += a.partial[3 * q + 2];
     }
-    mean[threadIdx.x] = s / ar;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      s0 += __shfl_xor(s0, d, 64);
+      s1 += __shfl_xor(s1, d, 64);
+      ar += __shfl_xor(ar, d, 64);
+    }
+    if (threadIdx.x == 0) {
+      mean[0] = s0 / ar;
+      mean[1] = s1 / ar;
+    }
   }
   __syncthreads();
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -680,7 +758,7 @@ __global__ __launch_bounds__(RED) void stats_kernel(StatArgs a) {
 // ------------------------------------------------------------------------------------------
 // host side
 
-constexpr int WG_MAX_BLOCKS = 1024;
+constexpr int WG_MAX_BLOCKS = 256;
 constexpr int CONV_MAX_BLOCKS = 4096;
 constexpr int LEARN_GRAPH_CHUNK = 32;
 
@@ -836,7 +914,7 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
   const int lblocks = blocks_for(la.total, RED);
   seq.push_back(make_launch(reinterpret_cast<const void*>(&loss_kernel), dim3(lblocks), dim3(RED), la));
   SumArgs sa{net->red, net->scalars, lblocks, 1, 1.0 / (4.0 * (double)la.total)};
-  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(64), sa));
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(RED), sa));
 
   const double scale = 2.0 / (4.0 * (double)la.total);
   const u16* e = net->e4;
@@ -857,7 +935,7 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
     GradArgs ga{net->partial, net->grad + layer_offset(l), wblocks, L_CIS[l], L_COS[l], L_CIN[l],
                 L_COUT[l], scale};
     seq.push_back(make_launch(reinterpret_cast<const void*>(&grad_reduce_kernel),
-                              dim3(blocks_for(layer_params(l), 256)), dim3(256), ga));
+                              dim3(blocks_for(layer_params(l), GR_PARAMS)), dim3(256), ga));
     if (l > 0) {
       // error signals alternate between two buffers: layer 4 -> eA, 3 -> eB, 2 -> eA, ...
       u16* next = (l == 4 || e == net->eB) ? net->eA : net->eB;
@@ -907,18 +985,23 @@ void pair_launch(const tlb_grid* g, const tlb_grid* truth, float* m, float* y,
                             dim3(blocks_for(a.plane, 256)), dim3(256), a));
 }
 
+// the correction of grid g by d; with nparts == 0 the area-weighted sums are made here (one
+// block per row), otherwise they are already in proj[nparts][3]
 template <typename T>
 void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* proj,
-                    std::vector<tlbi_launch>& seq) {
-  ProjArgs pa{d, g->area, proj, g->p.n_phi, scale[0], scale[1]};
-  seq.push_back(make_launch(reinterpret_cast<const void*>(&proj_kernel), dim3(g->p.n_theta),
-                            dim3(RED), pa));
+                    int nparts, std::vector<tlbi_launch>& seq) {
+  if (nparts == 0) {
+    ProjArgs pa{d, g->area, proj, g->p.n_phi, scale[0], scale[1]};
+    seq.push_back(make_launch(reinterpret_cast<const void*>(&proj_kernel), dim3(g->p.n_theta),
+                              dim3(RED), pa));
+    nparts = g->p.n_theta;
+  }
   ApplyArgs<T> aa{};
   aa.f = static_cast<T*>(g->f[0]);
   aa.phi = static_cast<T*>(g->phi[0]);
   aa.d = d;
   aa.partial = proj;
-  aa.H = g->p.n_theta;
+  aa.nparts = nparts;
   aa.plane = (long long)g->p.n_theta * g->p.n_phi;
   for (int c = 0; c < 4; ++c) aa.scale[c] = scale[c];
   seq.push_back(make_launch(reinterpret_cast<const void*>(&apply_kernel<T>),
@@ -936,14 +1019,21 @@ void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) 
     pair_launch<double>(g, nullptr, net->mbuf, nullptr, seq);
   else
     pair_launch<float>(g, nullptr, net->mbuf, nullptr, seq);
-  forward_seq(net, net->mbuf, nullptr, 1, seq);
   float scale[4];
   for (int c = 0; c < 4; ++c)
     scale[c] = (net->d.apply_mask == 0 || ((net->d.apply_mask >> c) & 1u)) ? net->d.out_scale[c] : 0.0f;
+  forward_seq(net, net->mbuf, nullptr, 1, seq);
+  // the last layer also forms the area-weighted sums of the corrections
+  ConvArgs* last = reinterpret_cast<ConvArgs*>(seq.back().args);
+  last->proj = net->proj;
+  last->area = g->area;
+  last->s0 = scale[0];
+  last->s1 = scale[1];
+  const int nparts = (int)seq.back().grid.x;
   if (g->p.precision == 64)
-    apply_launches<double>(g, net->z, scale, net->proj, seq);
+    apply_launches<double>(g, net->z, scale, net->proj, nparts, seq);
   else
-    apply_launches<float>(g, net->z, scale, net->proj, seq);
+    apply_launches<float>(g, net->z, scale, net->proj, nparts, seq);
 }
 
 void drop_learn_graph(tlb_cnn* net) {
@@ -1073,7 +1163,7 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   alloc((void**)&net->scalars, 8 * 8);
   alloc((void**)&net->Jrow, net->H * 4);
   alloc((void**)&net->mbuf, net->HW * 16);
-  alloc((void**)&net->proj, net->H * 3 * 8);
+  alloc((void**)&net->proj, (size_t)(net->H > CONV_MAX_BLOCKS ? net->H : CONV_MAX_BLOCKS) * 3 * 8);
   if (e != hipSuccess) {
     free_net(net);
     return tlbi_fail(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -1208,7 +1298,7 @@ int32_t tlb_learn_stats(const float* data, int64_t count, void* hip_stream, doub
   std::vector<tlbi_launch> seq;
   seq.push_back(make_launch(reinterpret_cast<const void*>(&stats_kernel), dim3(blocks), dim3(RED), a));
   SumArgs s{part, part + blocks * 8, blocks, 8, 1.0};
-  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(64), s));
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(RED), s));
   int32_t rc = run_all(seq, stream);
   hipError_t e = hipStreamSynchronize(stream);
   if (rc == TLB_OK && e == hipSuccess)
@@ -1284,9 +1374,9 @@ int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections) {
   const float one[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   std::vector<tlbi_launch> seq;
   if (grid->p.precision == 64)
-    apply_launches<double>(grid, corrections, one, proj, seq);
+    apply_launches<double>(grid, corrections, one, proj, 0, seq);
   else
-    apply_launches<float>(grid, corrections, one, proj, seq);
+    apply_launches<float>(grid, corrections, one, proj, 0, seq);
   rc = run_all(seq, grid->stream);
   const hipError_t e = hipStreamSynchronize(grid->stream);
   (void)hipFree(proj);

@@ -38,6 +38,14 @@ def _steps(t, dt):
     return int(round(t / dt))
 
 
+def coarse_grid(pc, precision=32):
+    """A coarse grid with the stage kernel's tile height chosen by the autotuner (small grids
+    prefer short tiles: more workgroups in flight)."""
+    g = TorusGrid(pc, precision)
+    g.tile_rows = g.autotune()
+    return g
+
+
 def generate_pairs(p_fine, seeds, t_first, t_last, every, k=4, dt_factor=4, precision=32,
                    coarse_override=None, noise=None, net=None, leads=(0,), reject=None,
                    progress=print):
@@ -231,7 +239,7 @@ def evaluate(p_fine, net, seed, t_start, t_end, every_t, k=4, dt_factor=4, preci
     fine.set_state(inputs.spinodal_phi(p_fine, seed=seed),
                    *inputs.rest_moments(p_fine.n_theta, p_fine.n_phi))
     fine.step(_steps(t_start, p_fine.dt))
-    judge, lc, pl = TorusGrid(pc, precision), TorusGrid(pc, precision), TorusGrid(pc, precision)
+    judge, lc, pl = TorusGrid(pc, precision), coarse_grid(pc, precision), coarse_grid(pc, precision)
     restrict(fine, lc)
     restrict(fine, pl)
     rows = []
@@ -302,7 +310,7 @@ class LearnedCoarseRunner:
         ("fine", fine_grid) -- the latter after the fine solver has taken over."""
         pc = coarse_params(self.p_fine, self.k, self.dt_factor, **(self.coarse_override or {}))
         if self.accepted:
-            coarse = TorusGrid(pc, self.precision)
+            coarse = coarse_grid(pc, self.precision)
             restrict(fine_grid, coarse)
             learned_step(coarse, self.net, _steps(t_span, pc.dt))
             if coarse.invariants()[2] == 0:
