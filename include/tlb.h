@@ -15,6 +15,12 @@
  *     f   : T[16][n_theta][n_phi]       (phi index fastest)
  *     phi, n, u_theta, u_phi, mu : T[n_theta][n_phi]
  * u_theta, u_phi are the orthonormal (vielbein) components of the fluid velocity.
+ * Precision 32 stores each population as its deviation from the rest equilibrium of unit
+ * density, f_k - w_i w_j (w = (3 -/+ sqrt6)/12, the weights of the velocity set): the stored
+ * values are a few per cent of f, so FP32 rounding loses far less of the small per-step
+ * increments (it otherwise biases the mass by about 1e-2 over 1e6 steps).  tlb_set_state and
+ * tlb_get_state convert; a caller reading an FP32 grid's f buffers directly sees deviations.
+ * Precision 64 stores f_k itself.
  *
  * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
  * buffers); they must outlive the grid handle.  The library owns only its per-row geometry

@@ -569,6 +569,7 @@ __device__ __forceinline__ void node_moments(const T* f, const T* phi, long long
     nut += vel(k >> 2) * fk;
     nup += vel(k & 3) * fk;
   });
+  if constexpr (stores_deviation<T>()) n += 1.0;  // the stored values are f - w_i w_j
   out[0] = (double)phi[x];
   out[1] = n;
   out[2] = nut / n;
@@ -673,6 +674,7 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs<T> a) {
     nut += T(vel(k >> 2)) * fk[k];
     nup += T(vel(k & 3)) * fk[k];
   });
+  if constexpr (stores_deviation<T>()) n += T(1);  // the stored values are f - w_i w_j
   const T ut = nut / n, up = nup / n;
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;

@@ -69,6 +69,15 @@ __host__ __device__ constexpr double kh(int i, int m) {
                     hermite_e(3, vel(i)) * hermite_e(2, vel(m)) / 2.0 +
                     hermite_e(4, vel(i)) * hermite_e(3, vel(m)) / 6.0);
 }
+// sum_m K^H_{im} w_m and sum_m K^H_{im} v_m w_m: the velocity derivatives of the rest
+// equilibrium (of f = w and of f v^phi = v w)
+__host__ __device__ constexpr double kw(int i) {
+  return kh(i, 0) * wgt(0) + kh(i, 1) * wgt(1) + kh(i, 2) * wgt(2) + kh(i, 3) * wgt(3);
+}
+__host__ __device__ constexpr double kvw(int i) {
+  return kh(i, 0) * vel(0) * wgt(0) + kh(i, 1) * vel(1) * wgt(1) + kh(i, 2) * vel(2) * wgt(2) +
+         kh(i, 3) * vel(3) * wgt(3);
+}
 
 // ------------------------------------------------------------------------------------------
 // tile geometry of the stage kernel
@@ -113,6 +122,8 @@ struct RowCoef {
   T lap_p;       // 1 / (J_q^2 dphi^2)
   T inv_2Jdph;   // 1 / (2 J_q dphi)
   T inv_2rJdth;  // 1 / (2 r J_q dtheta)
+  T bsum_p;      // sum of bth_p: the theta advection of a theta-independent value (v > 0)
+  T bsum_m;      // sum of bth_m (v < 0)
 };
 
 template <typename T>
@@ -417,6 +428,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
         dth += rc.bth_m[o + 2] * buf[cN + o * LXT];
       });
     }
+    // deviation storage: the constant w_i w_j drops out of the phi differences (their
+    // weights sum to zero) but not out of the J-weighted theta differences
+    if constexpr (stores_deviation<T>())
+      dth += T(rest_offset<T>(k)) * (i >= 2 ? rc.bsum_p : rc.bsum_m);
     adv[k] = T(-vel(i)) * dth + (T(-vel(j)) * inv_Jdph) * dph;
     if (ring) {
       const T fr = buf[cR];
@@ -437,6 +452,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   });
 
   // ---- CH fluxes of the tile and the ring
+  // with deviation storage the sums above are n - 1; dn keeps that small difference exactly
+  const T dn = n;
+  if constexpr (stores_deviation<T>()) {
+    n += T(1);
+    rn += T(1);
+  }
   const T inv_n = T(1) / n;
   const T ut = nut * inv_n, up = nup * inv_n;
   const T phc = sPhi[(ly + 2) * LXT + lx + CX];
@@ -496,10 +517,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       dvt += T(kh(i, m)) * f[4 * m + j];
       dvp += T(kh(j, m)) * g[4 * i + m];
     });
+    if constexpr (stores_deviation<T>()) {
+      // the velocity derivatives of the stored constant w_i w_j, in closed form
+      dvt += T(wgt(j) * kw(i));
+      dvp += T(wgt(i)) * (Fph * T(kw(j)) + G * T(vel(i) * kvw(j)));
+    }
     const T xi = T(vel(i)) * ut + T(vel(j)) * up;
-    const T poly = c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
-    const T feq = (n * T(wgt(i) * wgt(j))) * poly;
-    const T L = adv[k] + (G * T(vel(j) * vel(j)) - Fth) * dvt - dvp + (feq - f[k]) * a.c.inv_tau;
+    T relax;  // f_eq - f, in the stored representation
+    if constexpr (stores_deviation<T>()) {
+      // f_eq - w_i w_j = w_i w_j (p1 + dn (1 + p1)), p1 = poly - 1, all small quantities
+      const T p1 = T(-0.5) * (ut * ut + up * up) + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
+      relax = T(wgt(i) * wgt(j)) * (p1 + dn * (T(1) + p1)) - f[k];
+    } else {
+      const T poly = c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
+      relax = (n * T(wgt(i) * wgt(j))) * poly - f[k];
+    }
+    const T L = adv[k] + (G * T(vel(j) * vel(j)) - Fth) * dvt - dvp + relax * a.c.inv_tau;
     const T ys = f[k] + dt * L;
     if (active) {
       T* dst = a.fout + k * a.plane + node;
@@ -556,7 +589,23 @@ __global__ __launch_bounds__(256) void tlb_init_feq_kernel(T* f, const T* n, con
     constexpr int k = decltype(kc)::value;
     constexpr int i = k >> 2, j = k & 3;
     const T xi = T(vel(i)) * a + T(vel(j)) * b;
-    f[k * plane + x] = (nn * T(wgt(i) * wgt(j))) * (c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0))));
+    if constexpr (stores_deviation<T>()) {
+      const T p1 = T(-0.5) * (a * a + b * b) + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
+      f[k * plane + x] = T(wgt(i) * wgt(j)) * (p1 + (nn - T(1)) * (T(1) + p1));
+    } else {
+      f[k * plane + x] = (nn * T(wgt(i) * wgt(j))) * (c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0))));
+    }
+  });
+}
+
+// between full populations and the stored representation: f += sign * rest_offset
+template <typename T>
+__global__ __launch_bounds__(256) void tlb_offset_kernel(T* f, long long plane, T sign) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= plane) return;
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    f[k * plane + x] += sign * T(rest_offset<T>(k));
   });
 }
 
@@ -578,6 +627,7 @@ __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* p
     nut += T(vel(k >> 2)) * fk;
     nup += T(vel(k & 3)) * fk;
   });
+  if constexpr (stores_deviation<T>()) n += T(1);
   if (n_out) n_out[x] = n;
   if (ut_out) ut_out[x] = nut / n;
   if (up_out) up_out[x] = nup / n;
@@ -625,6 +675,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, con
         bad += isfinite(fk) ? 0.0 : 1.0;
         n += fk;
       }
+      if constexpr (stores_deviation<T>()) n += 1.0;
       const double ph = (double)phi[x];
       bad += isfinite(ph) ? 0.0 : 1.0;
       rm += n;
@@ -678,6 +729,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
       double n = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) n += (double)f[k * plane + x];
+      if constexpr (stores_deviation<T>()) n += 1.0;
       rphi += ph;
       rp += n + A * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
     }
@@ -759,14 +811,21 @@ void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
     const double th = q * dth;
     const double J = Jat(th);
     RowCoef<T>& rc = rows[q];
+    double sp = 0.0, sm = 0.0;
     for (int o = -3; o <= 2; ++o) {
       const int qq = ((q + o) % nt + nt) % nt;
-      rc.bth_p[o + 3] = T(uw5p(o) * Jat(qq * dth) / (p.r * J * dth));
+      const double b = uw5p(o) * Jat(qq * dth) / (p.r * J * dth);
+      rc.bth_p[o + 3] = T(b);
+      sp += b;
     }
     for (int o = -2; o <= 3; ++o) {
       const int qq = ((q + o) % nt + nt) % nt;
-      rc.bth_m[o + 2] = T(uw5m(o) * Jat(qq * dth) / (p.r * J * dth));
+      const double b = uw5m(o) * Jat(qq * dth) / (p.r * J * dth);
+      rc.bth_m[o + 2] = T(b);
+      sm += b;
     }
+    rc.bsum_p = T(sp);
+    rc.bsum_m = T(sm);
     rc.inv_Jdph = T(1.0 / (J * dph));
     rc.J = T(J);
     rc.G = T(flat ? 0.0 : std::sin(th) / J);
@@ -1103,6 +1162,15 @@ int32_t init_feq_t(tlb_grid* g, const void* n, const void* ut, const void* up) {
 }
 
 template <typename T>
+int32_t offset_t(tlb_grid* g, void* f, T sign) {
+  const long long plane = (long long)g->p.n_theta * g->p.n_phi;
+  hipLaunchKernelGGL(tlb_offset_kernel<T>, dim3((int)((plane + 255) / 256)), dim3(256), 0,
+                     g->stream, static_cast<T*>(f), plane, sign);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+template <typename T>
 int32_t moments_t(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu) {
   const long long plane = (long long)g->p.n_theta * g->p.n_phi;
   const int blocks = (int)((plane + 255) / 256);
@@ -1283,6 +1351,7 @@ int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n
   if (f) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(g->f[0], f, 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+    if (g->p.precision == 32) return offset_t<float>(g, g->f[0], -1.0f);
     return TLB_OK;
   }
   return g->p.precision == 64 ? init_feq_t<double>(g, n, ut, up)
@@ -1307,9 +1376,14 @@ int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
   g_last_error.clear();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
-  if (f)
+  if (f) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(f, g->f[0], 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+    if (g->p.precision == 32) {
+      int32_t rc = offset_t<float>(g, f, 1.0f);
+      if (rc != TLB_OK) return rc;
+    }
+  }
   if (phi)
     TLB_HIP_CHECK(
         hipMemcpyAsync(phi, g->phi[0], plane_bytes, hipMemcpyDeviceToDevice, g->stream));

@@ -55,6 +55,20 @@ __host__ __device__ constexpr double wgt(int i) {
   return (i == 0 || i == 3) ? (3.0 - SQRT6) / 12.0 : (3.0 + SQRT6) / 12.0;
 }
 
+// Storage of the populations.  FP32 grids store each population as its deviation from the
+// rest equilibrium of unit density, f_k - w_i w_j (k = 4 i + j): the stored values are a few
+// per cent of f, so their rounding is correspondingly finer, and the small per-step increments
+// (relaxation, forcing) are not lost against O(0.1) values.  FP64 grids store f_k itself.
+template <typename T>
+__host__ __device__ constexpr bool stores_deviation() {
+  return std::is_same<T, float>::value;
+}
+// the value subtracted before storage: w_i w_j for deviation storage, else 0
+template <typename T>
+__host__ __device__ constexpr double rest_offset(int k) {
+  return stores_deviation<T>() ? wgt(k >> 2) * wgt(k & 3) : 0.0;
+}
+
 template <int I>
 using ic = std::integral_constant<int, I>;
 // compile-time loop: fn(ic<B>{}), fn(ic<B+1>{}), ..., fn(ic<E-1>{})

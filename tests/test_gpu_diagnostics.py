@@ -32,9 +32,9 @@ def test_diagnostics_match_oracle_fp64(torch_cuda):
 @pytest.mark.parametrize("tau", [0.6, 2.0])
 def test_spinodal_fp32_against_fp64(torch_cuda, tau):
     """512 x 1280 spinodal workload, 50,000 steps (t = 20) in both precisions from the same
-    seeded phi: L_d(t) agrees within 2 % once domains have formed (t >= 6).  Mass: FP64
-    drifts by less than 1e-11; FP32 storage loses the small BGK corrections added to O(0.1)
-    populations by rounding, measured 1.8e-3 over the run at tau = 0.6 (bar 5e-3)."""
+    seeded phi: L_d(t) agrees within 2 % once domains have formed (t >= 6) (measured 4e-4).
+    Mass: FP64 drifts by less than 1e-11; FP32, which stores deviations from the rest
+    equilibrium, by 8e-8 (bar 1e-6; plain FP32 storage drifted by 1.8e-3)."""
     from paper_1904_10070_amd import TorusGrid
     p = inputs.spinodal_workload(tau)
     phi = inputs.spinodal_phi(p, seed=7)
@@ -60,4 +60,4 @@ def test_spinodal_fp32_against_fp64(torch_cuda, tau):
           flush=True)
     assert np.all(np.diff(l64[t >= 6]) > -0.05 * l64[t >= 6][:-1])   # coarsening, L_d grows
     assert rel[t >= 6].max() <= 0.02
-    assert drift[64] < 1e-11 and drift[32] < 5e-3
+    assert drift[64] < 1e-11 and drift[32] < 1e-6
