@@ -50,3 +50,44 @@ def test_profiles_of_uniform_and_banded_fields():
     assert np.allclose(d["p_avg"], 1 + 0.1 * np.sin(th) + A * (-0.5 * ph ** 2 + 0.75 * ph ** 4),
                        rtol=0, atol=1e-14)
     assert d["L_I"] > 0
+
+
+# -- structure-factor length (oracle/structure.py) ------------------------------------------
+
+def brute_structure(phi, r, R):
+    """The definition written out: a double loop over modes and nodes."""
+    H, W = phi.shape
+    d = phi - phi.mean()
+    s0 = s1 = 0.0
+    for m in range(H):
+        mm = m if m <= H // 2 - (1 if H % 2 == 0 else 0) else m - H
+        if H % 2 == 0 and m == H // 2:
+            mm = -H // 2
+        for mp in range(W):
+            mmp = mp if mp < (W + 1) // 2 else mp - W
+            acc = 0j
+            for q in range(H):
+                for s in range(W):
+                    acc += d[q, s] * np.exp(-2j * np.pi * (m * q / H + mp * s / W))
+            S = abs(acc) ** 2
+            s0 += S
+            s1 += np.hypot(mm / r, mmp / R) * S
+    return 2 * np.pi * s0 / s1
+
+
+def test_structure_length_definition_and_closed_forms():
+    from oracle import structure as S
+    rng = np.random.default_rng(3)
+    phi = rng.uniform(-1, 1, (6, 10))
+    assert abs(S.structure_length(phi, 1.0, 2.5)[0] - brute_structure(phi, 1.0, 2.5)) < 1e-12
+    H, W, r, R = 32, 48, 1.0, 2.5
+    th = 2 * np.pi * np.arange(H) / H
+    ph = 2 * np.pi * np.arange(W) / W
+    # a single mode: all power at |k| = 3 / r, or 2 / R, or sqrt((3/r)^2 + (2/R)^2)
+    assert abs(S.structure_length(np.cos(3 * th)[:, None] + 0 * ph, r, R)[0] - 2 * np.pi * r / 3) < 1e-12
+    assert abs(S.structure_length(0 * th[:, None] + np.cos(2 * ph), r, R)[0] - np.pi * R) < 1e-12
+    both = np.cos(3 * th)[:, None] * np.cos(2 * ph)[None, :]
+    assert abs(S.structure_length(both, r, R)[0] - 2 * np.pi / np.hypot(3 / r, 2 / R)) < 1e-12
+    # Parseval: sum S = N sum (phi - <phi>)^2
+    d = phi - phi.mean()
+    assert abs(S.structure_length(phi, 1.0, 2.5)[1] - phi.size * (d * d).sum()) < 1e-10
