@@ -138,6 +138,17 @@ int32_t tlb_invariants(tlb_grid* grid, double out[3]);
  * for the stream only when out is non-NULL.  Errors: TLB_EINVAL, TLB_EHIP.                 */
 int32_t tlb_diagnostics(tlb_grid* grid, double out[2], double* phi_avg, double* p_avg);
 
+/* Structure-factor coarsening length of phi, in the coordinate-space approximation of the
+ * torus: S(m, m') = |DFT of phi over the node grid|^2 at mode numbers m (theta) and m' (phi),
+ * wavenumbers k = (m / r, m' / R) with signed mode numbers (the Nyquist mode counts as -n/2),
+ * the zero mode left out; out[0] = L_S = 2 pi sum S / sum |k| S, out[1] = sum S,
+ * out[2] = sum |k| S (host array of 3 doubles).  A direct DFT in FP64 (rows, then columns),
+ * fixed-order sums; the spinodal coarsening runs of section IV are the use.  The first call
+ * allocates a workspace of about 16 n_theta n_phi bytes, kept until tlb_destroy.
+ * n_phi <= 8192 and n_theta <= 4096.  Waits for the stream.  Errors: TLB_EINVAL,
+ * TLB_ENOMEM, TLB_EHIP.                                                                    */
+int32_t tlb_structure_length(tlb_grid* grid, double out[3]);
+
 /* Release the handle and the library's own device memory (not the caller's buffers).      */
 void tlb_destroy(tlb_grid* grid);
 

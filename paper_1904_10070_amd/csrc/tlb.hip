@@ -32,6 +32,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "tlb.h"
 #include "tlb_internal.h"
@@ -766,6 +767,75 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
   }
 }
 
+// Structure-factor length: a direct DFT of phi in FP64, rows then columns.  The zero mode is
+// left out, so the mean of phi need not be removed.  tw holds exp(-2 pi i j / n) for the row
+// length n_phi followed by the column length n_theta.
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void tlb_dft_rows_kernel(const T* phi,
+                                                                  const double2* tw, double2* X,
+                                                                  int np) {
+  extern __shared__ double srow[];  // the row, n_phi values
+  const int q = blockIdx.x;
+  for (int s0 = threadIdx.x; s0 < np; s0 += RED_THREADS)
+    srow[s0] = (double)phi[(long long)q * np + s0];
+  __syncthreads();
+  for (int m = threadIdx.x; m < np; m += RED_THREADS) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;  // (m s) mod n_phi
+    for (int s0 = 0; s0 < np; ++s0) {
+      const double2 w = tw[idx];
+      re += srow[s0] * w.x;
+      im += srow[s0] * w.y;
+      idx += m;
+      if (idx >= np) idx -= np;
+    }
+    X[(long long)q * np + m] = make_double2(re, im);
+  }
+}
+
+// one block per phi mode m': the column transform, |Y|^2, and the sums of S and |k| S
+__global__ __launch_bounds__(RED_THREADS) void tlb_dft_cols_kernel(const double2* X,
+                                                                  const double2* tw, int nt,
+                                                                  int np, double r, double R,
+                                                                  double* partial) {
+  extern __shared__ double2 scol[];  // the column, n_theta complex values
+  __shared__ double sh[2][RED_THREADS / 64];
+  const int mp = blockIdx.x;
+  for (int q = threadIdx.x; q < nt; q += RED_THREADS) scol[q] = X[(long long)q * np + mp];
+  __syncthreads();
+  const double kp = (mp <= (np - 1) / 2 ? mp : mp - np) / R;
+  double s0 = 0.0, s1 = 0.0;
+  for (int m = threadIdx.x; m < nt; m += RED_THREADS) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;  // (m q) mod n_theta
+    for (int q = 0; q < nt; ++q) {
+      const double2 w = tw[idx];
+      const double2 x = scol[q];
+      re += x.x * w.x - x.y * w.y;
+      im += x.x * w.y + x.y * w.x;
+      idx += m;
+      if (idx >= nt) idx -= nt;
+    }
+    const double S = (m == 0 && mp == 0) ? 0.0 : re * re + im * im;
+    const double kt = (m <= (nt - 1) / 2 ? m : m - nt) / r;
+    s0 += S;
+    s1 += sqrt(kt * kt + kp * kp) * S;
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = s0;
+    sh[1][w] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int i = 0; i < RED_THREADS / 64; ++i) t += sh[threadIdx.x][i];
+    partial[2 * mp + threadIdx.x] = t;
+  }
+}
+
 __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_final_kernel(const double* partial,
                                                                       int nblocks,
                                                                       double* out) {
@@ -1252,9 +1322,72 @@ void tlbi_stage_launch(const tlb_grid* g, int stage, tlbi_launch* out) {
   }
 }
 
+namespace {
+
+// workspace: X [nt][np] complex, twiddles (np + nt) complex, partials 2 np doubles
+size_t dft_bytes(const tlb_grid* g) {
+  const size_t nt = g->p.n_theta, np = g->p.n_phi;
+  return (nt * np + np + nt) * sizeof(double2) + 2 * np * sizeof(double);
+}
+
+template <typename T>
+int32_t structure_t(tlb_grid* g, double out[3]) {
+  const int nt = g->p.n_theta, np = g->p.n_phi;
+  if ((size_t)np * sizeof(double) > 64 * 1024 || (size_t)nt * sizeof(double2) > 64 * 1024)
+    return fail(TLB_EINVAL, "structure factor: a row or column exceeds the 64 KB of LDS per block");
+  double2* X = nullptr;
+  double2* tw = nullptr;
+  double* part = nullptr;
+  if (!g->dft_work) {
+    hipError_t e = hipMalloc(&g->dft_work, dft_bytes(g));
+    if (e != hipSuccess) {
+      g->dft_work = nullptr;
+      return fail(TLB_ENOMEM, std::string("structure factor workspace: ") + hipGetErrorString(e));
+    }
+    std::vector<double2> h(np + nt);
+    for (int j = 0; j < np; ++j)
+      h[j] = make_double2(std::cos(2.0 * M_PI * j / np), -std::sin(2.0 * M_PI * j / np));
+    for (int j = 0; j < nt; ++j)
+      h[np + j] = make_double2(std::cos(2.0 * M_PI * j / nt), -std::sin(2.0 * M_PI * j / nt));
+    X = static_cast<double2*>(g->dft_work);
+    TLB_HIP_CHECK(hipMemcpy(X + (size_t)nt * np, h.data(), h.size() * sizeof(double2),
+                            hipMemcpyHostToDevice));
+  }
+  X = static_cast<double2*>(g->dft_work);
+  tw = X + (size_t)nt * np;
+  part = reinterpret_cast<double*>(tw + np + nt);
+  hipLaunchKernelGGL(tlb_dft_rows_kernel<T>, dim3(nt), dim3(RED_THREADS), np * sizeof(double),
+                     g->stream, static_cast<const T*>(g->phi[0]), tw, X, np);
+  TLB_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(tlb_dft_cols_kernel, dim3(np), dim3(RED_THREADS), nt * sizeof(double2),
+                     g->stream, X, tw + np, nt, np, g->p.r, g->p.R, part);
+  TLB_HIP_CHECK(hipGetLastError());
+  std::vector<double> h(2 * (size_t)np);
+  TLB_HIP_CHECK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               g->stream));
+  TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
+  double s0 = 0.0, s1 = 0.0;
+  for (int mp = 0; mp < np; ++mp) {
+    s0 += h[2 * mp];
+    s1 += h[2 * mp + 1];
+  }
+  out[0] = s1 > 0.0 ? 2.0 * M_PI * s0 / s1 : INFINITY;
+  out[1] = s0;
+  out[2] = s1;
+  return TLB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tlb_last_error(void) { return g_last_error.c_str(); }
+
+int32_t tlb_structure_length(tlb_grid* g, double out[3]) {
+  g_last_error.clear();
+  if (!g || !out) return fail(TLB_EINVAL, "grid or out is NULL");
+  return g->p.precision == 64 ? structure_t<double>(g, out) : structure_t<float>(g, out);
+}
 
 int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffers,
                               void* hip_stream, tlb_grid** out) {
@@ -1334,6 +1467,7 @@ void tlb_destroy(tlb_grid* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
   drop_graph(g);
+  if (g->dft_work) (void)hipFree(g->dft_work);
   (void)hipFree(g->rows);
   (void)hipFree(g->area);
   (void)hipFree(g->partial);

@@ -25,6 +25,7 @@ struct tlb_grid {
   int ty;                     // tile height of the stage kernel (4, 8 or 16)
   hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
   bool chunk_tried;
+  void* dft_work;  // structure-factor workspace (built on first use): row transforms and twiddles
 };
 
 // Records `msg` as the thread's last error and returns `code`.

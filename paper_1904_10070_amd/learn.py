@@ -231,8 +231,10 @@ def _phi_l2(a, b):
 def evaluate(p_fine, net, seed, t_start, t_end, every_t, k=4, dt_factor=4, precision=32,
              coarse_override=None, progress=print):
     """Hand the fine state at t_start over to a learned and a plain coarse grid and run all
-    three to t_end; every every_t report L_d (fine grid, restricted fine on the coarse grid,
-    learned, plain) and phi L2 differences against the restricted fine state."""
+    three to t_end; every every_t report the coarsening lengths L_d = A_total / L_I and L_S
+    (structure factor) of the fine grid, of the restricted fine state on the coarse grid (the
+    judge), of the learned and of the plain coarse grid, and the relative L2 difference of phi
+    from the restricted fine state."""
     import torch
     pc = coarse_params(p_fine, k, dt_factor, **(coarse_override or {}))
     fine = TorusGrid(p_fine, precision)
@@ -253,14 +255,17 @@ def evaluate(p_fine, net, seed, t_start, t_end, every_t, k=4, dt_factor=4, preci
         pl.step(coarse_steps)
         restrict(fine, judge)
         L = [g.diagnostics(profiles=False)["L_d"] for g in (fine, judge, lc, pl)]
+        S = [g.structure_length()[0] for g in (fine, judge, lc, pl)]
         row = dict(t=t_start + c * every_t, L_fine=L[0], L_judge=L[1], L_learned=L[2],
-                   L_plain=L[3], phi_l2_learned=_phi_l2(lc, judge),
-                   phi_l2_plain=_phi_l2(pl, judge), nonfinite=lc.invariants()[2])
+                   L_plain=L[3], LS_fine=S[0], LS_judge=S[1], LS_learned=S[2], LS_plain=S[3],
+                   phi_l2_learned=_phi_l2(lc, judge), phi_l2_plain=_phi_l2(pl, judge),
+                   nonfinite=lc.invariants()[2])
         rows.append(row)
         if progress:
-            progress(f"eval t={row['t']:.1f}: L fine {L[0]:.4f} judge {L[1]:.4f} learned {L[2]:.4f} "
-                     f"({(L[2] - L[1]) / L[1]:+.3f}) plain {L[3]:.4f} ({(L[3] - L[1]) / L[1]:+.3f}) "
-                     f"phi L2 learned {row['phi_l2_learned']:.3f} plain {row['phi_l2_plain']:.3f}")
+            progress(f"eval t={row['t']:.1f}: L_d judge {L[1]:.4f} learned {(L[2] - L[1]) / L[1]:+.3f} "
+                     f"plain {(L[3] - L[1]) / L[1]:+.3f} | L_S judge {S[1]:.4f} learned "
+                     f"{(S[2] - S[1]) / S[1]:+.3f} plain {(S[3] - S[1]) / S[1]:+.3f} | phi L2 "
+                     f"learned {row['phi_l2_learned']:.3f} plain {row['phi_l2_plain']:.3f}")
     torch.cuda.synchronize()
     return rows
 
@@ -282,7 +287,7 @@ class LearnedCoarseRunner:
     """The learned coarse step with the plain fine solver as judge and fallback.
 
     validate() runs the judged evaluation on a held-out seed and accepts the network only if
-    the relative L_d error stays within max_error over the window; run() then advances a fine
+    the relative errors of L_S and L_d stay within max_error over the window; run() then advances a fine
     state handed over at some time by the learned coarse step, and falls back to the fine
     solver (from the handed-over state) if the network was not accepted or the coarse state
     turns non-finite."""
@@ -298,8 +303,11 @@ class LearnedCoarseRunner:
     def validate(self, seed, t_start, t_end, every_t, progress=print):
         rows = evaluate(self.p_fine, self.net, seed, t_start, t_end, every_t, self.k,
                         self.dt_factor, self.precision, self.coarse_override, progress)
-        err = max(abs(r["L_learned"] - r["L_judge"]) / r["L_judge"] for r in rows)
-        err_plain = max(abs(r["L_plain"] - r["L_judge"]) / r["L_judge"] for r in rows)
+        # the larger of the L_S and L_d errors
+        err = max(max(abs(r[k + "_learned"] - r[k + "_judge"]) / r[k + "_judge"]
+                      for k in ("L", "LS")) for r in rows)
+        err_plain = max(max(abs(r[k + "_plain"] - r[k + "_judge"]) / r[k + "_judge"]
+                            for k in ("L", "LS")) for r in rows)
         self.accepted = err <= self.max_error and all(r["nonfinite"] == 0 for r in rows)
         self.report = dict(rows=rows, L_error=err, L_error_plain=err_plain,
                            accepted=self.accepted)

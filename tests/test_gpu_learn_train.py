@@ -2,11 +2,12 @@
 judge (spinodal coarsening, 512 x 1280 fine -> 128 x 320 coarse with a 4x time step).
 
 The plain coarse grid keeps the fine interface width, which it cannot resolve: its interfaces
-pin and its coarsening length L_d falls behind the fine solution's (about -9 % four time units
-after the hand-over).  The tests train a network from scratch on a reduced set of solver-made
-pairs and check the held-out one-step loss and the judged L_d error against the plain step's;
-and they check that the committed weights (train_coarse.py) meet the stated bar of 2 % on a
-seed held out from their training and selection.
+pin and its coarsening lengths fall behind the fine solution's (L_d about -9 %, the
+structure-factor length L_S about -22 % four time units after the hand-over).  The tests train
+a network from scratch on a reduced set of solver-made pairs and check the held-out one-step
+loss and the judged L_S and L_d errors against the plain step's; and they check that the
+committed weights (train_coarse.py) meet the stated bar of 2 % on a seed held out from their
+training and selection.
 """
 import numpy as np
 import pytest
@@ -19,9 +20,11 @@ MASK = 13                       # phi and the velocity are corrected
 LOSS_W = (1.0, 0.0, 0.25, 0.25)
 
 
-def l_errors(rows):
-    e = [abs(r["L_learned"] - r["L_judge"]) / r["L_judge"] for r in rows]
-    p = [abs(r["L_plain"] - r["L_judge"]) / r["L_judge"] for r in rows]
+def l_errors(rows, key="L"):
+    """Largest relative error of the learned and of the plain coarse run for L_d (key "L") or
+    the structure-factor length L_S (key "LS")."""
+    e = [abs(r[key + "_learned"] - r[key + "_judge"]) / r[key + "_judge"] for r in rows]
+    p = [abs(r[key + "_plain"] - r[key + "_judge"]) / r[key + "_judge"] for r in rows]
     return max(e), max(p)
 
 
@@ -44,29 +47,33 @@ def test_training_from_scratch_gains_over_plain_coarse_step(torch_cuda):
     assert after < 0.05 * zero
     rows = L.evaluate(pf, net, seed=7, t_start=20.0, t_end=24.0, every_t=2.0)
     err, err_plain = l_errors(rows)
-    print(f"largest L_d error over t in [20, 24]: learned {err:.4f}, plain {err_plain:.4f}",
-          flush=True)
+    errs, errs_plain = l_errors(rows, "LS")
+    print(f"largest error over t in [20, 24]: L_d learned {err:.4f}, plain {err_plain:.4f}; "
+          f"L_S learned {errs:.4f}, plain {errs_plain:.4f}", flush=True)
     assert all(r["nonfinite"] == 0 for r in rows)
-    assert err < 0.5 * err_plain
+    assert err < 0.5 * err_plain and errs < 0.5 * errs_plain
     assert rows[-1]["phi_l2_learned"] < rows[-1]["phi_l2_plain"]
 
 
 @pytest.mark.timeout(300)
 def test_committed_weights_meet_the_bar(torch_cuda):
     """Hand-over at t = 20 (seed 7, used neither for training nor for choosing the weights),
-    judged to t = 28 (5000 coarse steps): L_d within 2 % of the restricted fine solution,
-    where the plain coarse step is off by more than 10 %."""
+    judged to t = 30 (6250 coarse steps): the structure-factor length L_S and L_d within 2 % of
+    those of the restricted fine solution, where the plain coarse step is off by more than 10 %
+    (L_S: 30 %)."""
     from paper_1904_10070_amd import learn as L, train_coarse
     params, meta = train_coarse.load(0.6)
     assert 7 not in meta["recipe"]["train_seeds"] and meta["validation"]["seed"] != 7
     net = train_coarse.network_from(meta, params)
     pf = inputs.spinodal_workload(0.6)
-    rows = L.evaluate(pf, net, seed=7, t_start=20.0, t_end=28.0, every_t=2.0)
+    rows = L.evaluate(pf, net, seed=7, t_start=20.0, t_end=30.0, every_t=2.0)
     err, err_plain = l_errors(rows)
-    print(f"committed weights, seed 7, t in [20, 28]: largest L_d error learned {err:.4f}, "
-          f"plain {err_plain:.4f}; phi L2 at t=28 learned {rows[-1]['phi_l2_learned']:.3f} "
-          f"plain {rows[-1]['phi_l2_plain']:.3f}", flush=True)
-    assert err <= 0.02 and err_plain > 0.10
+    errs, errs_plain = l_errors(rows, "LS")
+    print(f"committed weights, seed 7, t in [20, 30]: largest error L_S learned {errs:.4f} "
+          f"plain {errs_plain:.4f}, L_d learned {err:.4f} plain {err_plain:.4f}; phi L2 at "
+          f"t=30 learned {rows[-1]['phi_l2_learned']:.3f} plain {rows[-1]['phi_l2_plain']:.3f}",
+          flush=True)
+    assert errs <= 0.02 and err <= 0.02 and err_plain > 0.10 and errs_plain > 0.10
 
 
 @pytest.mark.timeout(300)
