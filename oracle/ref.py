@@ -17,6 +17,7 @@ from . import build as _build
 
 FLAT = 1
 CH_NO_ADVECTION = 2
+WENO5 = 8
 
 _DP = ctypes.POINTER(ctypes.c_double)
 
@@ -63,6 +64,10 @@ def _lib(bits=64):
         lib.tlbref_steps.restype = ctypes.c_int64
         lib.tlbref_diagnostics.argtypes = [vp, _DP, _DP, _DP]
         lib.tlbref_diagnostics.restype = ctypes.c_int
+        lib.tlbref_uw5_face.argtypes = [_DP]
+        lib.tlbref_uw5_face.restype = ctypes.c_double
+        lib.tlbref_weno5_face.argtypes = [_DP, ctypes.c_double]
+        lib.tlbref_weno5_face.restype = ctypes.c_double
         lib.tlbref_real_bytes.argtypes = []
         lib.tlbref_real_bytes.restype = ctypes.c_int
         _LIBS[bits] = lib
@@ -74,6 +79,18 @@ def _ptr(a):
         return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_DP)
+
+
+def uw5_face(h):
+    """UW5 face value between h[2] and h[3] from h[0..4] (upwind side on the left)."""
+    a = np.ascontiguousarray(h, dtype=np.float64)
+    return float(_lib().tlbref_uw5_face(_ptr(a)))
+
+
+def weno5_face(h, eps=1e-6):
+    """WENO-5 (Jiang-Shu) face value between h[2] and h[3] from h[0..4]."""
+    a = np.ascontiguousarray(h, dtype=np.float64)
+    return float(_lib().tlbref_weno5_face(_ptr(a), float(eps)))
 
 
 def velocity_set():

@@ -24,6 +24,8 @@
  * Readings where the paper defers to its supplementary material (not available):
  *   - spatial derivative in the Boltzmann advection: conservative finite-difference flux form,
  *     face values by the fifth-order upwind (UW5) linear reconstruction, upwind by sign(v);
+ *     with TLBREF_WENO5 the same faces by the nonlinear WENO-5 reconstruction of Jiang and
+ *     Shu (J. Comput. Phys. 126, 1996), whose weights reduce to the UW5 ones on smooth data;
  *   - Cahn-Hilliard: second-order central flux form with face averages;
  *   - time stepping: three-stage strong-stability-preserving Runge-Kutta (Shu-Osher form) on
  *     the joint state (f, phi);
@@ -44,6 +46,8 @@ typedef TLBREF_REAL real;
 
 #define TLBREF_FLAT 1u            /* J = R, G = 0: the flat periodic Cartesian limit        */
 #define TLBREF_CH_NO_ADVECTION 2u /* drop the u phi flux from Cahn-Hilliard                */
+#define TLBREF_WENO5 8u           /* face values by the nonlinear WENO-5 reconstruction     */
+#define TLBREF_WENO_EPS 1e-6      /* the smoothness regulariser of Jiang and Shu            */
 
 #define TLBREF_OK 0
 #define TLBREF_EINVAL (-1)
@@ -141,6 +145,31 @@ static real feq_one(const tlbref_grid* g, int i, int j, real n, real ut, real up
  * transport velocity; the stencil is h_{-2}..h_{+2}. */
 static real uw5_face(real hm2, real hm1, real h0, real hp1, real hp2) {
   return (RC(2) * hm2 - RC(13) * hm1 + RC(47) * h0 + RC(27) * hp1 - RC(3) * hp2) / RC(60);
+}
+
+/* WENO-5 reconstruction of h at the same face (Jiang and Shu 1996): the three third-order
+ * candidates on the sub-stencils {-2,-1,0}, {-1,0,1}, {0,1,2}, weighted by d_k / (eps + b_k)^2
+ * with the linear weights d = (1, 6, 3) / 10 and the smoothness indicators b_k, normalised. */
+static real weno5_face_eps(real hm2, real hm1, real h0, real hp1, real hp2, real eps) {
+  const real c0 = (RC(2) * hm2 - RC(7) * hm1 + RC(11) * h0) / RC(6);
+  const real c1 = (-hm1 + RC(5) * h0 + RC(2) * hp1) / RC(6);
+  const real c2 = (RC(2) * h0 + RC(5) * hp1 - hp2) / RC(6);
+  const real a0 = hm2 - RC(2) * hm1 + h0, b0 = hm2 - RC(4) * hm1 + RC(3) * h0;
+  const real a1 = hm1 - RC(2) * h0 + hp1, b1 = hm1 - hp1;
+  const real a2 = h0 - RC(2) * hp1 + hp2, b2 = RC(3) * h0 - RC(4) * hp1 + hp2;
+  const real s0 = RC(13) / RC(12) * a0 * a0 + RC(0.25) * b0 * b0;
+  const real s1 = RC(13) / RC(12) * a1 * a1 + RC(0.25) * b1 * b1;
+  const real s2 = RC(13) / RC(12) * a2 * a2 + RC(0.25) * b2 * b2;
+  const real w0 = RC(0.1) / ((eps + s0) * (eps + s0));
+  const real w1 = RC(0.6) / ((eps + s1) * (eps + s1));
+  const real w2 = RC(0.3) / ((eps + s2) * (eps + s2));
+  return (w0 * c0 + w1 * c1 + w2 * c2) / (w0 + w1 + w2);
+}
+
+/* the face value of the configured scheme */
+static real face_value(int weno, real hm2, real hm1, real h0, real hp1, real hp2) {
+  return weno ? weno5_face_eps(hm2, hm1, h0, hp1, hp2, RC(TLBREF_WENO_EPS))
+              : uw5_face(hm2, hm1, h0, hp1, hp2);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -259,7 +288,9 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
     }
 
   /* advection (eq. boltz_tor): -(v_j / J) d_phi f - v_i / (r J) d_theta (J f), conservative
-   * finite differences with UW5 face values taken from the upwind side of each velocity.   */
+   * finite differences with UW5 (or WENO-5) face values taken from the upwind side of each
+   * velocity.                                                                               */
+  const int weno = (g->p.flags & TLBREF_WENO5) != 0;
 #pragma omp parallel for schedule(static)
   for (int q = 0; q < nt; ++q)
     for (int s = 0; s < np; ++s)
@@ -272,12 +303,12 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
           real face_e, face_w;
           if (vp > 0) { /* h at s-3 .. s+2 */
             for (int o = 0; o < 6; ++o) hp[o] = f[FIDX(g, k, q, wrap(s - 3 + o, np))];
-            face_e = uw5_face(hp[1], hp[2], hp[3], hp[4], hp[5]);
-            face_w = uw5_face(hp[0], hp[1], hp[2], hp[3], hp[4]);
+            face_e = face_value(weno, hp[1], hp[2], hp[3], hp[4], hp[5]);
+            face_w = face_value(weno, hp[0], hp[1], hp[2], hp[3], hp[4]);
           } else { /* h at s-2 .. s+3; the upwind side is s+1 and beyond */
             for (int o = 0; o < 6; ++o) hp[o] = f[FIDX(g, k, q, wrap(s - 2 + o, np))];
-            face_e = uw5_face(hp[5], hp[4], hp[3], hp[2], hp[1]);
-            face_w = uw5_face(hp[4], hp[3], hp[2], hp[1], hp[0]);
+            face_e = face_value(weno, hp[5], hp[4], hp[3], hp[2], hp[1]);
+            face_w = face_value(weno, hp[4], hp[3], hp[2], hp[1], hp[0]);
           }
           real adv_ph = -(vp / (g->J[q] * dph)) * (face_e - face_w);
           /* theta direction: nodal flux h = J f */
@@ -288,15 +319,15 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
               int qq = wrap(q - 3 + o, nt);
               ht[o] = g->J[qq] * f[FIDX(g, k, qq, s)];
             }
-            face_n = uw5_face(ht[1], ht[2], ht[3], ht[4], ht[5]);
-            face_s = uw5_face(ht[0], ht[1], ht[2], ht[3], ht[4]);
+            face_n = face_value(weno, ht[1], ht[2], ht[3], ht[4], ht[5]);
+            face_s = face_value(weno, ht[0], ht[1], ht[2], ht[3], ht[4]);
           } else {
             for (int o = 0; o < 6; ++o) {
               int qq = wrap(q - 2 + o, nt);
               ht[o] = g->J[qq] * f[FIDX(g, k, qq, s)];
             }
-            face_n = uw5_face(ht[5], ht[4], ht[3], ht[2], ht[1]);
-            face_s = uw5_face(ht[4], ht[3], ht[2], ht[1], ht[0]);
+            face_n = face_value(weno, ht[5], ht[4], ht[3], ht[2], ht[1]);
+            face_s = face_value(weno, ht[4], ht[3], ht[2], ht[1], ht[0]);
           }
           real adv_th = -(vt / (r * g->J[q] * dth)) * (face_n - face_s);
           g->adv[FIDX(g, k, q, s)] = adv_ph + adv_th;
@@ -532,6 +563,14 @@ int tlbref_rhs_terms(tlbref_grid* g, const double* f, const double* phi, double*
 }
 
 /* Constants of the velocity set in double: v[4], w[4], K[16], Kt[16] (row-major, K[i][m]). */
+/* The face reconstructions on their own (for tests): UW5, and WENO-5 with a given eps.      */
+double tlbref_uw5_face(const double h[5]) {
+  return (double)uw5_face(RC(h[0]), RC(h[1]), RC(h[2]), RC(h[3]), RC(h[4]));
+}
+double tlbref_weno5_face(const double h[5], double eps) {
+  return (double)weno5_face_eps(RC(h[0]), RC(h[1]), RC(h[2]), RC(h[3]), RC(h[4]), RC(eps));
+}
+
 void tlbref_velocity_set(double v[4], double w[4], double K[16], double Kt[16]) {
   double K2[4][4], Kt2[4][4];
   velocity_set(v, w, K2, Kt2);
