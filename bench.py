@@ -278,7 +278,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
     ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64",
-                                       "ensemble32", "learned32", "learnedstep32", "train32"],
+                                       "ensemble32", "learned32", "learnedstep32", "train32",
+                                       "weno32"],
                     help="time a single workload/precision (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
@@ -290,8 +291,11 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1904_10070_amd import inputs, load_library
+    from paper_1904_10070_amd import inputs, load_library, WENO5
     load_library()
+
+    class inputs_mod:  # flag values of the C interface used below
+        WENO5_FLAG = WENO5
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     if args.copy_calibration:
@@ -322,7 +326,9 @@ def main():
         return
     if args.only:
         wl, prec = args.only[:-2], int(args.only[-2:])
-        p = inputs.spinodal_workload(0.6) if wl == "spinodal" else inputs.roofline_workload()
+        p = inputs.spinodal_workload(0.6) if wl in ("spinodal", "weno") else inputs.roofline_workload()
+        if wl == "weno":
+            p = p.with_(flags=WENO5)
         d = gpu_leg(p, prec, args.steps, args.warmup)
         print(json.dumps({"workload": f"{wl} {p.n_theta}x{p.n_phi}", "precision": prec,
                           "value": d["nups"], "unit": "node-updates/s",
@@ -374,6 +380,12 @@ def main():
         d = gpu_leg(pd, 64, 2000, args.warmup, phi=inputs.drop_workload_phi(pd, seed=1))
         out["drop64x160_fp64"] = {"value": d["nups"], "unit": "node-updates/s",
                                   "ms_per_step": d["t_step"] * 1e3, "steps": 2000}
+        # the WENO-5 advection variant (nonlinear face weights: arithmetic-bound)
+        d = gpu_leg(p.with_(flags=inputs_mod.WENO5_FLAG), 32, max(10, args.steps // 4), args.warmup)
+        out["weno5_fp32"] = {"value": d["nups"], "unit": "node-updates/s",
+                             "ms_per_step": d["t_step"] * 1e3, "steps": max(10, args.steps // 4),
+                             "vs_uw5": d["nups"] / head["nups"],
+                             "hbm_frac": d["achieved_gbs"] / HBM_PEAK_GBS}
         out["ensemble64_fp32"] = ensemble_leg(max(10, args.steps // 10), 5)
         out["learned_coarse_fp32"] = learned_leg(head["t_step"])
     if not args.no_cpu:

@@ -54,6 +54,9 @@ extern "C" {
 #define TLB_CH_NO_ADVECTION 2u /* drop -div(u phi) from the Cahn-Hilliard equation          */
 #define TLB_NO_GRAPH 4u        /* tlb_step_n launches every kernel itself instead of replaying *
                                 * a prebuilt graph of 32 time steps (same results, bit-exact) */
+#define TLB_WENO5 8u           /* advection face values by the nonlinear WENO-5 reconstruction *
+                                * (Jiang-Shu weights, eps = 1e-6) instead of the linear UW5   *
+                                * one; tiles of 8 rows only, not in batches                   */
 
 /* Physical and numerical parameters, in the paper's units (k_B T = m = 1, so the kinematic
  * viscosity is nu = tau, eq. nu).

@@ -21,6 +21,7 @@ TLB_ENONFINITE = -4
 FLAT = 1
 CH_NO_ADVECTION = 2
 NO_GRAPH = 4
+WENO5 = 8
 
 EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",

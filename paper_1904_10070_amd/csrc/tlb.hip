@@ -110,6 +110,48 @@ __host__ __device__ constexpr double uw5p(int o) {
 }
 __host__ __device__ constexpr double uw5m(int o) { return -uw5p(-o); }
 
+// WENO-5 face value (Jiang and Shu, J. Comput. Phys. 126, 1996) between h0 and hp1 from the
+// upwind side: third-order candidates on {-2,-1,0}, {-1,0,1}, {0,1,2}, combined with weights
+// d_k / (eps + beta_k)^2 (d = 1/10, 6/10, 3/10; beta_k the smoothness indicators), normalised.
+// On smooth data the weights tend to d and the face value to the UW5 one.
+constexpr double WENO_EPS = 1e-6;
+
+template <typename T>
+__device__ __forceinline__ T weno5(T hm2, T hm1, T h0, T hp1, T hp2) {
+  const T q0 = (T(2) * hm2 - T(7) * hm1 + T(11) * h0) * T(1.0 / 6.0);
+  const T q1 = (T(5) * h0 - hm1 + T(2) * hp1) * T(1.0 / 6.0);
+  const T q2 = (T(2) * h0 + T(5) * hp1 - hp2) * T(1.0 / 6.0);
+  const T d0 = hm2 - T(2) * hm1 + h0, e0 = hm2 - T(4) * hm1 + T(3) * h0;
+  const T d1 = hm1 - T(2) * h0 + hp1, e1 = hm1 - hp1;
+  const T d2 = h0 - T(2) * hp1 + hp2, e2 = T(3) * h0 - T(4) * hp1 + hp2;
+  const T b0 = T(WENO_EPS) + T(13.0 / 12.0) * d0 * d0 + T(0.25) * e0 * e0;
+  const T b1 = T(WENO_EPS) + T(13.0 / 12.0) * d1 * d1 + T(0.25) * e1 * e1;
+  const T b2 = T(WENO_EPS) + T(13.0 / 12.0) * d2 * d2 + T(0.25) * e2 * e2;
+  const T a0 = T(0.1) / (b0 * b0), a1 = T(0.6) / (b1 * b1), a2 = T(0.3) / (b2 * b2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// The two WENO-5 flux differences of population k = 4 i + j at a node: b points at the node in
+// the LDS population tile (rows LXT apart), Jnb holds J of the rows q-3..q+3.  Along phi the
+// stored values are used as they are (the reconstruction is shift-invariant, so deviations
+// give the same differences); along theta the flux h = J f of the full population.
+template <typename T, int I, int J, int K>
+__device__ __forceinline__ void weno_advection(const T* b, const T (&Jnb)[7], T inv_rJdth,
+                                               T& dph, T& dth) {
+  if constexpr (J >= 2)
+    dph = weno5(b[-2], b[-1], b[0], b[1], b[2]) - weno5(b[-3], b[-2], b[-1], b[0], b[1]);
+  else
+    dph = weno5(b[3], b[2], b[1], b[0], b[-1]) - weno5(b[2], b[1], b[0], b[-1], b[-2]);
+  T h[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) h[o] = Jnb[o] * (b[(o - 3) * LXT] + T(rest_offset<T>(K)));
+  if constexpr (I >= 2)
+    dth = weno5(h[1], h[2], h[3], h[4], h[5]) - weno5(h[0], h[1], h[2], h[3], h[4]);
+  else
+    dth = weno5(h[6], h[5], h[4], h[3], h[2]) - weno5(h[5], h[4], h[3], h[2], h[1]);
+  dth *= inv_rJdth;
+}
+
 // Per theta-row coefficients (one record per row q), all derived on the host in FP64.
 template <typename T>
 struct RowCoef {
@@ -293,8 +335,11 @@ struct Ring {
 
 // One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
 // described by `a`, by a block of Tile<TY>::NT threads.
-template <typename T, bool VEC, int TY>
+template <typename T, bool VEC, int TY, bool WENO = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, const int ty) {
+// (the body is device code: the host pass of the single-source compiler skips it; with both
+// advection variants instantiated, that pass otherwise rejects the call from the batch kernel)
+#if defined(__HIP_DEVICE_COMPILE__)
   using TL = Tile<TY>;
   constexpr int NT = TL::NT, LY = TL::LY, PY = TL::PY, NRING = TL::NRING;
   constexpr int D = Ring<T>::D;
@@ -381,6 +426,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const int cN = (ly + HY) * LXT + lx + CX;  // this node in the population tile
   const int cR = (ry + HY) * LXT + rx + CX;  // the ring node
   const T inv_Jdph = rc.inv_Jdph;
+  // WENO: J of rows q-3..q+3 (wavefront-uniform scalar loads) and 1 / (r J dtheta)
+  T Jnb[7];
+  T inv_rJdth = T(0);
+  if constexpr (WENO) {
+#pragma unroll
+    for (int o = 0; o < 7; ++o) Jnb[o] = a.rows[wrapi(qw + o - 3, nt)].J;
+    inv_rJdth = T(2) * rc.inv_2rJdth;
+  }
 
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -400,7 +453,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     nut += T(vel(i)) * f[k];
     nup += T(vel(j)) * f[k];
     // phi direction: sum_o uw5(o) f_{s+o}, upwind side by the sign of v_j
-    T dph;
+    T dph, dth;
+    if constexpr (WENO) {
+      weno_advection<T, i, j, k>(buf + cN, Jnb, inv_rJdth, dph, dth);
+    } else {
     if constexpr (j >= 2) {
       dph = T(uw5p(-3)) * buf[cN - 3];
       static_for<-2, 3>([&](auto oc) {
@@ -415,7 +471,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       });
     }
     // theta direction: sum_o uw5(o) J_{q+o} / (r J_q dtheta) f_{q+o}
-    T dth;
     if constexpr (i >= 2) {
       dth = rc.bth_p[0] * buf[cN - 3 * LXT];
       static_for<-2, 3>([&](auto oc) {
@@ -433,6 +488,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     // weights sum to zero) but not out of the J-weighted theta differences
     if constexpr (stores_deviation<T>())
       dth += T(rest_offset<T>(k)) * (i >= 2 ? rc.bsum_p : rc.bsum_m);
+    }
     adv[k] = T(-vel(i)) * dth + (T(-vel(j)) * inv_Jdph) * dph;
     if (ring) {
       const T fr = buf[cR];
@@ -540,14 +596,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
     }
   });
+#endif
 }
 
-template <typename T, bool VEC, int TY>
+template <typename T, bool VEC, int TY, bool WENO = false>
 __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   int tx, ty;
   band_tile(tile, a.ntx, a.nty, tx, ty);
-  stage_tile<T, VEC, TY>(a, tx, ty);
+  stage_tile<T, VEC, TY, WENO>(a, tx, ty);
 }
 
 // One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
@@ -572,7 +629,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
     const StageArgs<T> a = table[3 * lo + stage - 1];
     int tx, ty;
     band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
-    stage_tile<T, VEC, TY>(a, tx, ty);
+    stage_tile<T, VEC, TY, false>(a, tx, ty);
     __syncthreads();  // the next tile reuses the LDS tiles
   }
 }
@@ -968,6 +1025,10 @@ const void* stage_fn_ty(int ty) {
 
 template <typename T>
 const void* stage_fn(const tlb_grid* g) {
+  if (g->p.flags & TLB_WENO5)  // the WENO variant exists for the default tile height only
+    return vec_ok<T>(g->p.n_phi)
+               ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true>)
+               : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, true>);
   return vec_ok<T>(g->p.n_phi) ? stage_fn_ty<T, true>(g->ty) : stage_fn_ty<T, false>(g->ty);
 }
 
@@ -1296,7 +1357,7 @@ int32_t check_params(const tlb_params* p) {
   if (!std::isfinite(p->A)) return fail(TLB_EINVAL, "A must be finite");
   if (p->precision != 32 && p->precision != 64)
     return fail(TLB_EINVAL, "precision must be 32 or 64");
-  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH))
+  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5))
     return fail(TLB_EINVAL, "unknown flag");
   return TLB_OK;
 }
@@ -1540,6 +1601,8 @@ int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
   g_last_error.clear();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (rows != 4 && rows != 8 && rows != 16) return fail(TLB_EINVAL, "tile rows must be 4, 8 or 16");
+  if ((g->p.flags & TLB_WENO5) && rows != DEFAULT_TY)
+    return fail(TLB_EINVAL, "the WENO-5 variant runs with tiles of 8 rows only");
   if (g->ty != rows) {
     g->ty = rows;
     drop_graph(g);
@@ -1550,6 +1613,10 @@ int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
 int32_t tlb_autotune(tlb_grid* g, int32_t* rows) {
   g_last_error.clear();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
+  if (g->p.flags & TLB_WENO5) {  // one tile height only
+    if (rows) *rows = g->ty;
+    return TLB_OK;
+  }
   return g->p.precision == 64 ? autotune_t<double>(g, rows) : autotune_t<float>(g, rows);
 }
 
@@ -1564,6 +1631,8 @@ int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tl
       return fail(TLB_EINVAL, "all grids of a batch must have the same precision");
     for (int j = 0; j < i; ++j)
       if (grids[j] == grids[i]) return fail(TLB_EINVAL, "a grid appears twice in the batch");
+    if (grids[i]->p.flags & TLB_WENO5)
+      return fail(TLB_EINVAL, "the WENO-5 variant is not available in batches");
   }
   tlb_batch* b = new (std::nothrow) tlb_batch{};
   if (!b) return fail(TLB_ENOMEM, "host allocation failed");

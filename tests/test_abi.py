@@ -48,7 +48,7 @@ def params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=1.0), dict(n_theta=0), dict(n_phi=-3),
                                  dict(dt=0.0), dict(tau=0.0), dict(kappa=-1.0), dict(M=-0.1),
-                                 dict(precision=16), dict(flags=8), dict(A=float("nan")),
+                                 dict(precision=16), dict(flags=16), dict(A=float("nan")),
                                  dict(n_theta=100000, n_phi=100000, precision=64)])
 def test_create_rejects_bad_parameters(lib, bad):
     p = params(**bad)
@@ -92,6 +92,21 @@ def test_null_handles_rejected(lib):
     assert lib.tlb_create_batch(None, 0, None, ctypes.byref(h)) == binding.TLB_EINVAL
     lib.tlb_destroy_batch(None)
     lib.tlb_destroy(None)
+
+
+def test_weno_flag_is_accepted_by_validation(lib):
+    """Flag 8 passes parameter validation (the create call then fails only for want of a GPU
+    or succeeds on one); 16 does not."""
+    p = params(flags=8)
+    b = binding.Buffers()
+    for i in range(3):
+        b.f[i] = 0x1000 * (i + 1)
+        b.phi[i] = 0x1000 * (i + 4)
+    h = ctypes.c_void_p()
+    rc = lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(h))
+    assert rc != binding.TLB_EINVAL or b"flags" not in lib.tlb_last_error()
+    if h.value:
+        lib.tlb_destroy(h)
 
 
 def test_binding_refuses_to_run_without_gpu():

@@ -180,3 +180,32 @@ def test_graph_replay_matches_plain_launches_bitwise(torch_cuda):
         fa, pa = a.get_state()
         fb, pb = b.get_state()
         assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb), call
+
+
+@pytest.mark.parametrize("shape,flags", [((64, 160), 8), ((37, 150), 8), ((9, 70), 8 | 1),
+                                         ((24, 96), 8 | 2)])
+def test_weno5_variant_fp64(torch_cuda, shape, flags):
+    """The WENO-5 advection variant (flag 8) against the oracle's, alone and with the flat and
+    no-CH-advection flags, on a drop and on random states (ragged tiles)."""
+    nt, np_ = shape
+    if shape == (64, 160):
+        p = inputs.drop_workload().with_(flags=flags)
+        phi = inputs.drop_workload_phi(p, seed=1)
+        n, ut, up = inputs.rest_moments(nt, np_)
+        steps = 400
+    else:
+        p = inputs.TorusParams(1.0, 2.5, nt, np_, 0.5, 2e-3, 0.05, 0.3, 2e-4, flags)
+        phi, n, ut, up = inputs.random_state(p, seed=nt + np_)
+        steps = 25
+    compare_fp64(p, phi, n, ut, up, steps, flags_note=f"WENO flags={flags}")
+
+
+def test_weno5_variant_fp32_tolerance(torch_cuda):
+    p = inputs.drop_workload().with_(flags=8)
+    phi = inputs.drop_workload_phi(p, seed=1)
+    n, ut, up = inputs.rest_moments(p.n_theta, p.n_phi)
+    og, f_ref, phi_ref = oracle_run(p, phi, n, ut, up, 2000)
+    gg, f_gpu, phi_gpu = gpu_run(p, phi, n, ut, up, 2000, precision=32)
+    ef, ep = rel_linf(f_gpu, f_ref), rel_linf(phi_gpu, phi_ref)
+    print(f"WENO fp32 vs fp64 oracle: f {ef:.2e} phi {ep:.2e}", flush=True)
+    assert ef <= 1.5e-3 and ep <= 1e-3
