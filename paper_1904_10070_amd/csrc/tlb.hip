@@ -322,8 +322,11 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 }
 
 // population ring depth: copies of up to RING-1 populations are in flight while one is used
+#ifndef TLB_PREFETCH_Y0
+#define TLB_PREFETCH_Y0 0
+#endif
 #ifndef TLB_RING32
-#define TLB_RING32 4
+#define TLB_RING32 6
 #endif
 #ifndef TLB_RING64
 #define TLB_RING64 4
@@ -418,6 +421,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
 
   // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
+#if TLB_PREFETCH_Y0
+  // y^n at this node for the Runge-Kutta combine, loaded during the population loop
+  T yn[16];
+  const long long node_pf = (long long)qw * np + (s < np ? s : 0);
+#endif
   // moments of this node and of the ring node, both summed population by population in the
   // same order, so that a node's moments (and all that follows) do not depend on whether it
   // is inside a tile or in a neighbour's ring -- results are independent of the tile shape
@@ -448,6 +456,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     if constexpr (k >= 1 && k + D - 1 < 16)
       cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
     const T* buf = slot(ic<k>{});
+#if TLB_PREFETCH_Y0
+    if (a.has_y0) yn[k] = a.f0[k * a.plane + node_pf];
+#endif
     f[k] = buf[cN];
     n += f[k];
     nut += T(vel(i)) * f[k];
@@ -593,7 +604,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     const T ys = f[k] + dt * L;
     if (active) {
       T* dst = a.fout + k * a.plane + node;
+#if TLB_PREFETCH_Y0
+      *dst = y0 ? a0 * yn[k] + b1 * ys : ys;
+#else
       *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
+#endif
     }
   });
 #endif
