@@ -322,11 +322,16 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 }
 
 // population ring depth: copies of up to RING-1 populations are in flight while one is used
-#ifndef TLB_PREFETCH_Y0
-#define TLB_PREFETCH_Y0 0
+// y^n of the node (stages 2 and 3) is loaded during the population loop instead of in the
+// epilogue, which hides its latency; costs 16 (FP32) or 32 (FP64) VGPRs
+#ifndef TLB_PREFETCH_Y0_32
+#define TLB_PREFETCH_Y0_32 1
+#endif
+#ifndef TLB_PREFETCH_Y0_64
+#define TLB_PREFETCH_Y0_64 0
 #endif
 #ifndef TLB_RING32
-#define TLB_RING32 6
+#define TLB_RING32 4
 #endif
 #ifndef TLB_RING64
 #define TLB_RING64 4
@@ -334,6 +339,7 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 template <typename T>
 struct Ring {
   static constexpr int D = sizeof(T) == 4 ? TLB_RING32 : TLB_RING64;
+  static constexpr bool PREFETCH = sizeof(T) == 4 ? TLB_PREFETCH_Y0_32 : TLB_PREFETCH_Y0_64;
 };
 
 // One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
@@ -421,11 +427,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
 
   // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
-#if TLB_PREFETCH_Y0
   // y^n at this node for the Runge-Kutta combine, loaded during the population loop
-  T yn[16];
+  constexpr bool PF = Ring<T>::PREFETCH;
+  T yn[PF ? 16 : 1];
   const long long node_pf = (long long)qw * np + (s < np ? s : 0);
-#endif
+  T phin = T(0);
+  if constexpr (PF)
+    if (a.has_y0) phin = a.phi0[node_pf];
   // moments of this node and of the ring node, both summed population by population in the
   // same order, so that a node's moments (and all that follows) do not depend on whether it
   // is inside a tile or in a neighbour's ring -- results are independent of the tile shape
@@ -456,9 +464,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     if constexpr (k >= 1 && k + D - 1 < 16)
       cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
     const T* buf = slot(ic<k>{});
-#if TLB_PREFETCH_Y0
-    if (a.has_y0) yn[k] = a.f0[k * a.plane + node_pf];
-#endif
+    if constexpr (PF)
+      if (a.has_y0) yn[k] = a.f0[k * a.plane + node_pf];
     f[k] = buf[cN];
     n += f[k];
     nut += T(vel(i)) * f[k];
@@ -559,7 +566,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const bool y0 = a.has_y0;
   if (active) {
     const T ys = phc + dt * Lphi;
-    a.phiout[node] = y0 ? a0 * a.phi0[node] + b1 * ys : ys;
+    if constexpr (PF)
+      a.phiout[node] = y0 ? a0 * phin + b1 * ys : ys;
+    else
+      a.phiout[node] = y0 ? a0 * a.phi0[node] + b1 * ys : ys;
   }
 
   // ---- equilibrium (eq. feq) as a cubic in xi = v.u:
@@ -604,11 +614,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     const T ys = f[k] + dt * L;
     if (active) {
       T* dst = a.fout + k * a.plane + node;
-#if TLB_PREFETCH_Y0
-      *dst = y0 ? a0 * yn[k] + b1 * ys : ys;
-#else
-      *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
-#endif
+      if constexpr (PF)
+        *dst = y0 ? a0 * yn[k] + b1 * ys : ys;
+      else
+        *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
     }
   });
 #endif
