@@ -167,7 +167,7 @@ def learned_step_timing(steps=2000):
     for name, stepper in (("learned", lambda g, n: learned_step(g, net, n)),
                           ("plain", lambda g, n: g.step(n))):
         g = L.coarse_grid(pc, precision=32)
-        out["tile_rows"] = g.tile_rows
+        out[f"tile_rows_{name}"] = g.tile_rows
         g.set_state(inputs.spinodal_phi(pc, seed=7), *inputs.rest_moments(pc.n_theta, pc.n_phi))
         stepper(g, 64)
         torch.cuda.synchronize()

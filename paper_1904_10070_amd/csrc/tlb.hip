@@ -25,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1168,26 +1169,49 @@ int32_t time_launches(hipStream_t stream, int reps, Launch launch, float* ms) {
 }
 
 constexpr int TILE_CHOICES[3] = {4, 8, 16};
+constexpr int TUNE_ROUNDS = 3;
 
-// Autotuner: time stage-1 launches (they read the state and write only the stage-1 scratch
-// copy, so the state is unchanged) for every tile height and keep the fastest.
+// Repetitions per measurement: about 3 ms of work at 1.5e10 node-stages/s, at least 4 and at
+// most 200 (small grids need many launches before the launch noise averages out).
+int tune_reps(long long nodes) {
+  const long long r = 20000000LL / (nodes > 0 ? nodes : 1);
+  return (int)std::max(4LL, std::min(200LL, r));
+}
+
+// Index into TILE_CHOICES of the smallest time; the default height wins ties.
+int fastest(const float (&ms)[3]) {
+  int pick = 1;
+  for (int c = 0; c < 3; ++c)
+    if (ms[c] < ms[pick]) pick = c;
+  return pick;
+}
+
+// Autotuner: time pairs of stage-1 and stage-2 launches for every tile height (stage 1 reads
+// the state and writes the stage-1 copy, stage 2 reads both and writes the stage-2 copy, so the
+// state is unchanged, and stage 2 reads as much as stage 3 does); three interleaved rounds, the
+// best time of each height counts.
 template <typename T>
 int32_t autotune_t(tlb_grid* g, int32_t* chosen) {
-  float best = -1.0f;
-  int best_ty = DEFAULT_TY;
-  for (int ty : TILE_CHOICES) {
-    g->ty = ty;
-    float ms = 0.0f;
-    int32_t rc = time_launches(g->stream, 5, [&]() { return launch_stage<T>(g, 1); }, &ms);
-    if (rc != TLB_OK) return rc;
-    if (best < 0.0f || ms < best) {
-      best = ms;
-      best_ty = ty;
+  const int old_ty = g->ty;
+  const int reps = tune_reps((long long)g->p.n_theta * g->p.n_phi);
+  float best[3] = {0.0f, 0.0f, 0.0f};
+  for (int round = 0; round < TUNE_ROUNDS; ++round)
+    for (int c = 0; c < 3; ++c) {
+      g->ty = TILE_CHOICES[c];
+      float ms = 0.0f;
+      int32_t rc = time_launches(g->stream, reps, [&]() {
+        int32_t r = launch_stage<T>(g, 1);
+        return r == TLB_OK ? launch_stage<T>(g, 2) : r;
+      }, &ms);
+      if (rc != TLB_OK) {
+        g->ty = old_ty;
+        return rc;
+      }
+      if (round == 0 || ms < best[c]) best[c] = ms;
     }
-  }
-  g->ty = best_ty;
+  g->ty = TILE_CHOICES[fastest(best)];
   drop_graph(g);
-  if (chosen) *chosen = best_ty;
+  if (chosen) *chosen = g->ty;
   return TLB_OK;
 }
 
@@ -1285,23 +1309,30 @@ int32_t batch_step_t(tlb_batch* b, int64_t n) {
 
 template <typename T>
 int32_t batch_autotune_t(tlb_batch* b, int32_t* chosen) {
-  float best = -1.0f;
-  int best_ty = DEFAULT_TY;
-  for (int ty : TILE_CHOICES) {
-    b->ty = ty;
-    int32_t rc = batch_setup_t<T>(b);
-    if (rc != TLB_OK) return rc;
-    float ms = 0.0f;
-    rc = time_launches(b->stream, 5, [&]() { return batch_launch_t<T>(b, 1); }, &ms);
-    if (rc != TLB_OK) return rc;
-    if (best < 0.0f || ms < best) {
-      best = ms;
-      best_ty = ty;
+  long long nodes = 0;
+  for (int i = 0; i < b->n; ++i) nodes += (long long)b->grids[i]->p.n_theta * b->grids[i]->p.n_phi;
+  const int reps = tune_reps(nodes);
+  float best[3] = {0.0f, 0.0f, 0.0f};
+  for (int round = 0; round < TUNE_ROUNDS; ++round)
+    for (int c = 0; c < 3; ++c) {
+      b->ty = TILE_CHOICES[c];
+      int32_t rc = batch_setup_t<T>(b);
+      float ms = 0.0f;
+      if (rc == TLB_OK)
+        rc = time_launches(b->stream, reps, [&]() {
+          int32_t r = batch_launch_t<T>(b, 1);
+          return r == TLB_OK ? batch_launch_t<T>(b, 2) : r;
+        }, &ms);
+      if (rc != TLB_OK) {
+        b->ty = DEFAULT_TY;
+        (void)batch_setup_t<T>(b);
+        return rc;
+      }
+      if (round == 0 || ms < best[c]) best[c] = ms;
     }
-  }
-  b->ty = best_ty;
+  b->ty = TILE_CHOICES[fastest(best)];
   int32_t rc = batch_setup_t<T>(b);
-  if (chosen) *chosen = best_ty;
+  if (chosen) *chosen = b->ty;
   return rc;
 }
 
