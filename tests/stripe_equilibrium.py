@@ -3,7 +3,8 @@ of the paper: the equilibrium positions of Fig. tor_stripe_fork and the Laplace 
 of Fig. stripe_laplace).
 
 TEST INFRASTRUCTURE (imports the oracle's closed forms): run as
-`python -m tests.stripe_equilibrium [fork|laplace] [64|32] [t_end]` from the repository root.
+`python -m tests.stripe_equilibrium [fork|laplace] [64|32] [t_end] [N_theta (fork)]` from the
+repository root.
 
 Common set-up (the paper's): r = 0.8, R = 2, N_theta = 320 (N_phi = 64: the stripes do not
 depend on phi), A = 0.5, nu = M = 2.5e-3, dt = 5e-4, the stripe is the phi = -1 phase
@@ -67,8 +68,8 @@ def run_ensemble(starts, precision, t_end, every_t=1.0, progress=None):
     return t, [np.array(r) for r in recs], drift
 
 
-def fork(precision=64, t_end=3000.0, progress=None):
-    p = inputs.TorusParams(**BASE)
+def fork(precision=64, t_end=3000.0, progress=None, n_theta=320):
+    p = inputs.TorusParams(**dict(BASE, n_theta=n_theta))
     starts = [(p, 0.5 * math.pi, w * math.pi) for w in FORK_WIDTHS]
     t, recs, drift = run_ensemble(starts, precision, t_end, progress=progress)
     rows = []
@@ -122,8 +123,9 @@ def main(argv):
     prog = lambda t: print(f"  t = {t:.0f}", flush=True)
     if what == "fork":
         t_end = float(argv[3]) if len(argv) > 3 else 3000.0
-        t, rows = fork(prec, t_end, prog)
-        print(f"FP{prec}, t_end = {t_end:g}")
+        n_theta = int(argv[4]) if len(argv) > 4 else 320
+        t, rows = fork(prec, t_end, prog, n_theta)
+        print(f"FP{prec}, N_theta = {n_theta}, t_end = {t_end:g}")
         print("| width_0 | dA / dA_crit | paper | here | crossings of pi | last crossing | "
               "theta_c end | theta_eq | width end | width_eq |")
         print("|" + "---|" * 10)
