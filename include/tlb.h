@@ -15,12 +15,13 @@
  *     f   : T[16][n_theta][n_phi]       (phi index fastest)
  *     phi, n, u_theta, u_phi, mu : T[n_theta][n_phi]
  * u_theta, u_phi are the orthonormal (vielbein) components of the fluid velocity.
- * Precision 32 stores each population as its deviation from the rest equilibrium of unit
- * density, f_k - w_i w_j (w = (3 -/+ sqrt6)/12, the weights of the velocity set): the stored
- * values are a few per cent of f, so FP32 rounding loses far less of the small per-step
- * increments (it otherwise biases the mass by about 1e-2 over 1e6 steps).  tlb_set_state and
- * tlb_get_state convert; a caller reading an FP32 grid's f buffers directly sees deviations.
- * Precision 64 stores f_k itself.
+ * Precision 32 stores each population as its deviation from the rest equilibrium of a
+ * reference density, f_k - n_ref w_i w_j (w = (3 -/+ sqrt6)/12, the weights of the velocity
+ * set; n_ref = the area-weighted mean density of the state loaded by tlb_set_state, rounded to
+ * two significant digits): the stored values are a few per cent of f, so FP32 rounding loses
+ * far less of the small per-step increments (it otherwise biases the mass by about 1e-2 over
+ * 1e6 steps).  tlb_set_state and tlb_get_state convert; a caller reading an FP32 grid's f
+ * buffers directly sees deviations.  Precision 64 stores f_k itself.
  *
  * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
  * buffers); they must outlive the grid handle.  The library owns only its per-row geometry
@@ -98,7 +99,9 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
 /* Load a state.  phi (required) is copied into state copy 0.  If f is non-NULL it is copied
  * as the populations; otherwise the populations are set to the discrete equilibrium
  * f_eq(n, u) of eq. feq from the moment fields n, u_theta, u_phi (then all three required).
- * Device pointers of element type T; stream-ordered.  Errors: TLB_EINVAL, TLB_EHIP.        */
+ * Device pointers of element type T; stream-ordered for precision 64; precision 32 waits for
+ * the stream (it measures the state's mean density to choose the reference density of its
+ * storage, see Layout).  Errors: TLB_EINVAL, TLB_EHIP.                                      */
 int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void* n,
                       const void* u_theta, const void* u_phi);
 
@@ -121,7 +124,8 @@ int32_t tlb_get_moments(tlb_grid* grid, void* n, void* u_theta, void* u_phi, voi
                         void* mu);
 
 /* Copy the current state (checkpoint) into caller buffers (either may be NULL).
- * tlb_set_state(grid, f, phi, ...) with the same buffers restores it exactly.              */
+ * tlb_set_state(grid, f, phi, ...) with the same buffers restores it: exactly in precision
+ * 64, to the rounding of the conversion from and to the stored deviations in precision 32.  */
 int32_t tlb_get_state(tlb_grid* grid, void* f, void* phi);
 
 /* Conservation diagnostics of the current state, reduced in FP64 in a fixed order (hence

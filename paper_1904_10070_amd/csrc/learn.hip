@@ -556,11 +556,12 @@ struct MomArgs {
   float* m;        // [HW][4]
   float* y;        // [HW][4]
   long long plane;
+  double n_add, n_add2;  // what a node's population sum lacks of its density, per grid
 };
 
 template <typename T>
 __device__ __forceinline__ void node_moments(const T* f, const T* phi, long long plane,
-                                             long long x, double out[4]) {
+                                             long long x, double n_add, double out[4]) {
   double n = 0.0, nut = 0.0, nup = 0.0;
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -569,7 +570,7 @@ __device__ __forceinline__ void node_moments(const T* f, const T* phi, long long
     nut += vel(k >> 2) * fk;
     nup += vel(k & 3) * fk;
   });
-  if constexpr (stores_deviation<T>()) n += 1.0;  // the stored values are f - w_i w_j
+  n += n_add;  // FP32 grids store f - n_ref w_i w_j
   out[0] = (double)phi[x];
   out[1] = n;
   out[2] = nut / n;
@@ -581,11 +582,11 @@ __global__ __launch_bounds__(256) void moments_pair_kernel(MomArgs<T> a) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.plane) return;
   double m[4];
-  node_moments(a.f, a.phi, a.plane, x, m);
+  node_moments(a.f, a.phi, a.plane, x, a.n_add, m);
   reinterpret_cast<float4*>(a.m)[x] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
   if (a.f2) {
     double t[4];
-    node_moments(a.f2, a.phi2, a.plane, x, t);
+    node_moments(a.f2, a.phi2, a.plane, x, a.n_add2, t);
     reinterpret_cast<float4*>(a.y)[x] = make_float4((float)(t[0] - m[0]), (float)(t[1] - m[1]),
                                                     (float)(t[2] - m[2]), (float)(t[3] - m[3]));
   }
@@ -628,6 +629,7 @@ struct ApplyArgs {
   int nparts;
   long long plane;
   float scale[4];
+  T n_ref;  // reference density of the stored deviations (FP32)
 };
 
 template <typename T>
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs<T> a) {
     nut += T(vel(k >> 2)) * fk[k];
     nup += T(vel(k & 3)) * fk[k];
   });
-  if constexpr (stores_deviation<T>()) n += T(1);  // the stored values are f - w_i w_j
+  if constexpr (stores_deviation<T>()) n += a.n_ref;  // the stored values are f - n_ref w_i w_j
   const T ut = nut / n, up = nup / n;
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -820,6 +822,7 @@ struct tlb_cnn {
   hipGraphExec_t chunk_exec;
   const tlb_grid* chunk_grid;
   void* chunk_key[7];
+  unsigned chunk_version;  // the grid's version when the graph was built
 };
 
 namespace {
@@ -983,6 +986,8 @@ void pair_launch(const tlb_grid* g, const tlb_grid* truth, float* m, float* y,
   a.m = m;
   a.y = y;
   a.plane = (long long)g->p.n_theta * g->p.n_phi;
+  a.n_add = stores_deviation<T>() ? g->n_ref : 0.0;
+  a.n_add2 = truth && stores_deviation<T>() ? truth->n_ref : 0.0;
   seq.push_back(make_launch(reinterpret_cast<const void*>(&moments_pair_kernel<T>),
                             dim3(blocks_for(a.plane, 256)), dim3(256), a));
 }
@@ -1006,6 +1011,7 @@ void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* p
   aa.nparts = nparts;
   aa.plane = (long long)g->p.n_theta * g->p.n_phi;
   for (int c = 0; c < 4; ++c) aa.scale[c] = scale[c];
+  aa.n_ref = T(g->n_ref);
   seq.push_back(make_launch(reinterpret_cast<const void*>(&apply_kernel<T>),
                             dim3(blocks_for(aa.plane, 256)), dim3(256), aa));
 }
@@ -1075,6 +1081,7 @@ int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
     return tlbi_fail(TLB_EHIP, std::string("learned-step graph: ") + hipGetErrorString(e));
   }
   net->chunk_grid = g;
+  net->chunk_version = g->version;
   void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
                   reinterpret_cast<void*>((intptr_t)g->ty)};
   std::memcpy(net->chunk_key, key, sizeof(key));
@@ -1082,7 +1089,7 @@ int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
 }
 
 bool graph_matches(const tlb_cnn* net, const tlb_grid* g) {
-  if (!net->chunk_exec || net->chunk_grid != g) return false;
+  if (!net->chunk_exec || net->chunk_grid != g || net->chunk_version != g->version) return false;
   void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
                   reinterpret_cast<void*>((intptr_t)g->ty)};
   return std::memcmp(net->chunk_key, key, sizeof(key)) == 0;
@@ -1345,6 +1352,12 @@ int32_t tlb_restrict(const tlb_grid* fine, tlb_grid* coarse) {
                               dim3(blocks_for(a.plane_c, 256)), dim3(256), a));
   };
   if (pf.precision == 64) go(double{}); else go(float{});
+  // the restricted deviations are relative to the fine grid's reference density (restriction
+  // keeps it: it preserves constants and the area-weighted totals)
+  if (pf.precision == 32 && coarse->n_ref != fine->n_ref) {
+    coarse->n_ref = fine->n_ref;
+    ++coarse->version;
+  }
   return run_all(seq, coarse->stream);
 }
 

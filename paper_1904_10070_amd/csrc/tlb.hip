@@ -138,14 +138,14 @@ __device__ __forceinline__ T weno5(T hm2, T hm1, T h0, T hp1, T hp2) {
 // give the same differences); along theta the flux h = J f of the full population.
 template <typename T, int I, int J, int K>
 __device__ __forceinline__ void weno_advection(const T* b, const T (&Jnb)[7], T inv_rJdth,
-                                               T& dph, T& dth) {
+                                               T n_ref, T& dph, T& dth) {
   if constexpr (J >= 2)
     dph = weno5(b[-2], b[-1], b[0], b[1], b[2]) - weno5(b[-3], b[-2], b[-1], b[0], b[1]);
   else
     dph = weno5(b[3], b[2], b[1], b[0], b[-1]) - weno5(b[2], b[1], b[0], b[-1], b[-2]);
   T h[7];
 #pragma unroll
-  for (int o = 0; o < 7; ++o) h[o] = Jnb[o] * (b[(o - 3) * LXT] + T(rest_offset<T>(K)));
+  for (int o = 0; o < 7; ++o) h[o] = Jnb[o] * (b[(o - 3) * LXT] + n_ref * T(rest_offset<T>(K)));
   if constexpr (I >= 2)
     dth = weno5(h[1], h[2], h[3], h[4], h[5]) - weno5(h[0], h[1], h[2], h[3], h[4]);
   else
@@ -173,6 +173,7 @@ struct RowCoef {
 template <typename T>
 struct Consts {
   T A, kappa, M, inv_tau, inv_2rdth, dt;
+  T n_ref;  // reference density of the stored deviations (FP32)
   int ch_adv;
 };
 
@@ -443,6 +444,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const int cN = (ly + HY) * LXT + lx + CX;  // this node in the population tile
   const int cR = (ry + HY) * LXT + rx + CX;  // the ring node
   const T inv_Jdph = rc.inv_Jdph;
+  const T n_ref = a.c.n_ref;
   // WENO: J of rows q-3..q+3 (wavefront-uniform scalar loads) and 1 / (r J dtheta)
   T Jnb[7];
   T inv_rJdth = T(0);
@@ -474,7 +476,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     // phi direction: sum_o uw5(o) f_{s+o}, upwind side by the sign of v_j
     T dph, dth;
     if constexpr (WENO) {
-      weno_advection<T, i, j, k>(buf + cN, Jnb, inv_rJdth, dph, dth);
+      weno_advection<T, i, j, k>(buf + cN, Jnb, inv_rJdth, n_ref, dph, dth);
     } else {
     if constexpr (j >= 2) {
       dph = T(uw5p(-3)) * buf[cN - 3];
@@ -503,10 +505,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
         dth += rc.bth_m[o + 2] * buf[cN + o * LXT];
       });
     }
-    // deviation storage: the constant w_i w_j drops out of the phi differences (their
+    // deviation storage: the constant n_ref w_i w_j drops out of the phi differences (their
     // weights sum to zero) but not out of the J-weighted theta differences
     if constexpr (stores_deviation<T>())
-      dth += T(rest_offset<T>(k)) * (i >= 2 ? rc.bsum_p : rc.bsum_m);
+      dth += (n_ref * T(rest_offset<T>(k))) * (i >= 2 ? rc.bsum_p : rc.bsum_m);
     }
     adv[k] = T(-vel(i)) * dth + (T(-vel(j)) * inv_Jdph) * dph;
     if (ring) {
@@ -528,11 +530,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   });
 
   // ---- CH fluxes of the tile and the ring
-  // with deviation storage the sums above are n - 1; dn keeps that small difference exactly
+  // with deviation storage the sums above are n - n_ref; dn keeps that small difference
   const T dn = n;
   if constexpr (stores_deviation<T>()) {
-    n += T(1);
-    rn += T(1);
+    n += n_ref;
+    rn += n_ref;
   }
   const T inv_n = T(1) / n;
   const T ut = nut * inv_n, up = nup * inv_n;
@@ -597,16 +599,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       dvp += T(kh(j, m)) * g[4 * i + m];
     });
     if constexpr (stores_deviation<T>()) {
-      // the velocity derivatives of the stored constant w_i w_j, in closed form
-      dvt += T(wgt(j) * kw(i));
-      dvp += T(wgt(i)) * (Fph * T(kw(j)) + G * T(vel(i) * kvw(j)));
+      // the velocity derivatives of the stored constant n_ref w_i w_j, in closed form
+      dvt += n_ref * T(wgt(j) * kw(i));
+      dvp += n_ref * (T(wgt(i)) * (Fph * T(kw(j)) + G * T(vel(i) * kvw(j))));
     }
     const T xi = T(vel(i)) * ut + T(vel(j)) * up;
     T relax;  // f_eq - f, in the stored representation
     if constexpr (stores_deviation<T>()) {
-      // f_eq - w_i w_j = w_i w_j (p1 + dn (1 + p1)), p1 = poly - 1, all small quantities
+      // f_eq - n_ref w_i w_j = w_i w_j (n_ref p1 + dn (1 + p1)), p1 = poly - 1, all small
       const T p1 = T(-0.5) * (ut * ut + up * up) + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
-      relax = T(wgt(i) * wgt(j)) * (p1 + dn * (T(1) + p1)) - f[k];
+      relax = T(wgt(i) * wgt(j)) * (n_ref * p1 + dn * (T(1) + p1)) - f[k];
     } else {
       const T poly = c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
       relax = (n * T(wgt(i) * wgt(j))) * poly - f[k];
@@ -663,7 +665,8 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
 // f = f_eq(n, u) (eq. feq), one thread per node
 template <typename T>
 __global__ __launch_bounds__(256) void tlb_init_feq_kernel(T* f, const T* n, const T* ut,
-                                                          const T* up, long long plane) {
+                                                          const T* up, long long plane,
+                                                          T n_ref) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= plane) return;
   const T nn = n[x], a = ut[x], b = up[x];
@@ -674,21 +677,22 @@ __global__ __launch_bounds__(256) void tlb_init_feq_kernel(T* f, const T* n, con
     const T xi = T(vel(i)) * a + T(vel(j)) * b;
     if constexpr (stores_deviation<T>()) {
       const T p1 = T(-0.5) * (a * a + b * b) + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0)));
-      f[k * plane + x] = T(wgt(i) * wgt(j)) * (p1 + (nn - T(1)) * (T(1) + p1));
+      f[k * plane + x] = T(wgt(i) * wgt(j)) * (n_ref * p1 + (nn - n_ref) * (T(1) + p1));
     } else {
       f[k * plane + x] = (nn * T(wgt(i) * wgt(j))) * (c0 + xi * (c0 + xi * (T(0.5) + xi * T(1.0 / 6.0))));
     }
   });
 }
 
-// between full populations and the stored representation: f += sign * rest_offset
+// between full populations and the stored representation: f += scale * rest_offset
+// (scale = -n_ref stores, +n_ref restores, the difference of two n_ref changes the reference)
 template <typename T>
-__global__ __launch_bounds__(256) void tlb_offset_kernel(T* f, long long plane, T sign) {
+__global__ __launch_bounds__(256) void tlb_offset_kernel(T* f, long long plane, T scale) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= plane) return;
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    f[k * plane + x] += sign * T(rest_offset<T>(k));
+    f[k * plane + x] += scale * T(rest_offset<T>(k));
   });
 }
 
@@ -697,7 +701,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* phi, T* n_out,
                                                          T* ut_out, T* up_out, T* phi_out,
                                                          T* mu_out, const RowCoef<T>* rows,
-                                                         int nt, int np, T A, T kappa) {
+                                                         int nt, int np, T A, T kappa,
+                                                         T n_ref) {
   const long long plane = (long long)nt * np;
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= plane) return;
@@ -710,7 +715,7 @@ __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* p
     nut += T(vel(k >> 2)) * fk;
     nup += T(vel(k & 3)) * fk;
   });
-  if constexpr (stores_deviation<T>()) n += T(1);
+  if constexpr (stores_deviation<T>()) n += n_ref;
   if (n_out) n_out[x] = n;
   if (ut_out) ut_out[x] = nut / n;
   if (up_out) up_out[x] = nup / n;
@@ -741,7 +746,7 @@ template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, const T* phi,
                                                                 const double* area, int nt,
                                                                 int np, int rows_per_block,
-                                                                double* partial) {
+                                                                double n_add, double* partial) {
   __shared__ double s[3][RED_THREADS / 64];
   const int q_begin = blockIdx.x * rows_per_block;
   const int q_end = min(nt, q_begin + rows_per_block);
@@ -758,7 +763,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, con
         bad += isfinite(fk) ? 0.0 : 1.0;
         n += fk;
       }
-      if constexpr (stores_deviation<T>()) n += 1.0;
+      n += n_add;  // the reference density of deviation storage (else 0)
       const double ph = (double)phi[x];
       bad += isfinite(ph) ? 0.0 : 1.0;
       rm += n;
@@ -793,8 +798,9 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
                                                               const double* area,
                                                               const double* half_len, double r_dth,
                                                               double A, int nt, int np,
-                                                              int rows_per_block, double* phi_avg,
-                                                              double* p_avg, double* partial) {
+                                                              int rows_per_block, double n_add,
+                                                              double* phi_avg, double* p_avg,
+                                                              double* partial) {
   __shared__ double s[3][RED_THREADS / 64];
   const int q_begin = blockIdx.x * rows_per_block;
   const int q_end = min(nt, q_begin + rows_per_block);
@@ -812,7 +818,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
       double n = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) n += (double)f[k * plane + x];
-      if constexpr (stores_deviation<T>()) n += 1.0;
+      n += n_add;
       rphi += ph;
       rp += n + A * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
     }
@@ -940,8 +946,9 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_final_kernel(const dou
 // ------------------------------------------------------------------------------------------
 // host side: per-launch constants and the per-row geometry (appendix A), derived in FP64
 template <typename T>
-Consts<T> make_consts(const tlb_params& p) {
+Consts<T> make_consts(const tlb_params& p, double n_ref) {
   Consts<T> c{};
+  c.n_ref = T(n_ref);
   const double dth = 2.0 * M_PI / p.n_theta;
   c.A = T(p.A);
   c.kappa = T(p.kappa);
@@ -1005,6 +1012,7 @@ struct tlb_batch {
   int total_tiles;
   hipGraphExec_t chunk_exec;
   bool chunk_tried;
+  unsigned* versions;  // [n]: the grids' versions when the table was built
 };
 
 namespace {
@@ -1029,7 +1037,7 @@ StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   a.has_y0 = stage != 1;
   a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
   a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
-  a.c = make_consts<T>(g->p);
+  a.c = make_consts<T>(g->p, g->n_ref);
   return a;
 }
 
@@ -1131,8 +1139,10 @@ void drop_graph(tlb_grid* g) {
 template <typename T>
 int32_t step_n_t(tlb_grid* g, int64_t n) {
   const bool use_graph = !(g->p.flags & TLB_NO_GRAPH) && n >= GRAPH_CHUNK;
+  if (g->chunk_tried && g->chunk_version != g->version) drop_graph(g);  // stale arguments
   if (use_graph && !g->chunk_tried) {
     g->chunk_tried = true;
+    g->chunk_version = g->version;
     int32_t rc = build_chunk_graph<T>(g);
     if (rc != TLB_OK) return rc;
   }
@@ -1237,6 +1247,7 @@ int32_t batch_setup_t(tlb_batch* b) {
   }
   long long total = 0;
   for (int i = 0; i < b->n; ++i) {
+    b->versions[i] = b->grids[i]->version;
     tlb_grid tmp = *b->grids[i];
     tmp.ty = b->ty;
     for (int st = 1; st <= 3; ++st) tab[3 * i + st - 1] = stage_args<T>(&tmp, st);
@@ -1342,16 +1353,16 @@ int32_t init_feq_t(tlb_grid* g, const void* n, const void* ut, const void* up) {
   const int blocks = (int)((plane + 255) / 256);
   hipLaunchKernelGGL(tlb_init_feq_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
                      static_cast<T*>(g->f[0]), static_cast<const T*>(n),
-                     static_cast<const T*>(ut), static_cast<const T*>(up), plane);
+                     static_cast<const T*>(ut), static_cast<const T*>(up), plane, T(g->n_ref));
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
 
 template <typename T>
-int32_t offset_t(tlb_grid* g, void* f, T sign) {
+int32_t offset_t(tlb_grid* g, void* f, T scale) {
   const long long plane = (long long)g->p.n_theta * g->p.n_phi;
   hipLaunchKernelGGL(tlb_offset_kernel<T>, dim3((int)((plane + 255) / 256)), dim3(256), 0,
-                     g->stream, static_cast<T*>(f), plane, sign);
+                     g->stream, static_cast<T*>(f), plane, scale);
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
@@ -1365,17 +1376,19 @@ int32_t moments_t(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu)
                      static_cast<T*>(n), static_cast<T*>(ut), static_cast<T*>(up),
                      static_cast<T*>(phi), static_cast<T*>(mu),
                      static_cast<const RowCoef<T>*>(g->rows), g->p.n_theta, g->p.n_phi,
-                     T(g->p.A), T(g->p.kappa));
+                     T(g->p.A), T(g->p.kappa), T(g->n_ref));
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
 
+// n_add: what each node's population sum lacks of its density (the reference density of the
+// stored deviations; 0 for full populations)
 template <typename T>
-int32_t reduce_t(tlb_grid* g) {
+int32_t reduce_t(tlb_grid* g, double n_add) {
   hipLaunchKernelGGL(tlb_reduce_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0,
                      g->stream, static_cast<const T*>(g->f[0]),
                      static_cast<const T*>(g->phi[0]), g->area, g->p.n_theta, g->p.n_phi,
-                     g->rows_per_block, g->partial);
+                     g->rows_per_block, n_add, g->partial);
   TLB_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(tlb_reduce_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream,
                      g->partial, g->red_blocks, g->partial + 3 * g->red_blocks);
@@ -1389,11 +1402,40 @@ int32_t diag_t(tlb_grid* g, double* phi_avg, double* p_avg) {
   hipLaunchKernelGGL(tlb_diag_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0, g->stream,
                      static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]), g->area,
                      g->half_len, g->p.r * dth, g->p.A, g->p.n_theta, g->p.n_phi,
-                     g->rows_per_block, phi_avg, p_avg, g->partial);
+                     g->rows_per_block, stores_deviation<T>() ? g->n_ref : 0.0, phi_avg, p_avg,
+                     g->partial);
   TLB_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(tlb_reduce_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream,
                      g->partial, g->red_blocks, g->partial + 3 * g->red_blocks);
   TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
+// Reference density of FP32 storage for a state of area-weighted mean density `mean`: mean to
+// two significant digits (so exactly 1 for every state near unit density), as a float value;
+// 1 for a state without a positive finite mean.
+double reference_density(double mean) {
+  if (!(mean > 0.0) || !std::isfinite(mean)) return 1.0;
+  const double e = std::pow(10.0, std::floor(std::log10(mean)) - 1.0);
+  return (double)(float)(std::round(mean / e) * e);
+}
+
+void set_reference(tlb_grid* g, double n_ref) {
+  if (n_ref == g->n_ref) return;
+  g->n_ref = n_ref;
+  ++g->version;
+  drop_graph(g);
+}
+
+// area-weighted mean density of state copy 0 of an FP32 grid (waits for the stream)
+int32_t mean_density(tlb_grid* g, double n_add, double* mean) {
+  int32_t rc = reduce_t<float>(g, n_add);
+  if (rc != TLB_OK) return rc;
+  double out[3];
+  TLB_HIP_CHECK(hipMemcpyAsync(out, g->partial + 3 * g->red_blocks, 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, g->stream));
+  TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
+  *mean = out[0] / (4.0 * M_PI * M_PI * g->p.r * g->p.R);
   return TLB_OK;
 }
 
@@ -1531,6 +1573,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   g->stream = static_cast<hipStream_t>(hip_stream);
   g->elem = params->precision == 64 ? sizeof(double) : sizeof(float);
   g->ty = DEFAULT_TY;
+  g->n_ref = 1.0;
   const int nt = params->n_theta;
   g->rows_per_block = nt <= 512 ? 1 : (nt + 511) / 512;
   g->red_blocks = (nt + g->rows_per_block - 1) / g->rows_per_block;
@@ -1601,11 +1644,24 @@ int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n
   if (f) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(g->f[0], f, 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
-    if (g->p.precision == 32) return offset_t<float>(g, g->f[0], -1.0f);
-    return TLB_OK;
+    if (g->p.precision == 64) return TLB_OK;
+    double mean = 0.0;
+    int32_t rc = mean_density(g, 0.0, &mean);  // full populations: nothing to add
+    if (rc != TLB_OK) return rc;
+    set_reference(g, reference_density(mean));
+    return offset_t<float>(g, g->f[0], -float(g->n_ref));
   }
-  return g->p.precision == 64 ? init_feq_t<double>(g, n, ut, up)
-                              : init_feq_t<float>(g, n, ut, up);
+  if (g->p.precision == 64) return init_feq_t<double>(g, n, ut, up);
+  // FP32: equilibrium with the current reference density, then again with the one the state's
+  // mean density asks for if that differs
+  int32_t rc = init_feq_t<float>(g, n, ut, up);
+  double mean = 0.0;
+  if (rc == TLB_OK) rc = mean_density(g, g->n_ref, &mean);
+  if (rc != TLB_OK) return rc;
+  const double n_ref = reference_density(mean);
+  if (n_ref == g->n_ref) return TLB_OK;
+  set_reference(g, n_ref);
+  return init_feq_t<float>(g, n, ut, up);
 }
 
 int32_t tlb_step_n(tlb_grid* g, int64_t n_steps) {
@@ -1630,7 +1686,7 @@ int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(f, g->f[0], 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
     if (g->p.precision == 32) {
-      int32_t rc = offset_t<float>(g, f, 1.0f);
+      int32_t rc = offset_t<float>(g, f, float(g->n_ref));
       if (rc != TLB_OK) return rc;
     }
   }
@@ -1643,7 +1699,7 @@ int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
 int32_t tlb_invariants(tlb_grid* g, double out[3]) {
   g_last_error.clear();
   if (!g || !out) return fail(TLB_EINVAL, "grid or out is NULL");
-  int32_t rc = g->p.precision == 64 ? reduce_t<double>(g) : reduce_t<float>(g);
+  int32_t rc = g->p.precision == 64 ? reduce_t<double>(g, 0.0) : reduce_t<float>(g, g->n_ref);
   if (rc != TLB_OK) return rc;
   TLB_HIP_CHECK(hipMemcpyAsync(out, g->partial + 3 * g->red_blocks, 3 * sizeof(double),
                                hipMemcpyDeviceToHost, g->stream));
@@ -1696,6 +1752,12 @@ int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tl
     delete b;
     return fail(TLB_ENOMEM, "host allocation failed");
   }
+  b->versions = new (std::nothrow) unsigned[n];
+  if (!b->versions) {
+    delete[] b->grids;
+    delete b;
+    return fail(TLB_ENOMEM, "host allocation failed");
+  }
   b->n = n;
   b->precision = grids[0]->p.precision;
   b->ty = DEFAULT_TY;
@@ -1725,6 +1787,13 @@ int32_t tlb_batch_step_n(tlb_batch* b, int64_t n_steps) {
   g_last_error.clear();
   if (!b) return fail(TLB_EINVAL, "batch is NULL");
   if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
+  // a grid whose stage arguments changed since the table was built (a new reference density)
+  for (int i = 0; i < b->n; ++i)
+    if (b->versions[i] != b->grids[i]->version) {
+      int32_t rc = b->precision == 64 ? batch_setup_t<double>(b) : batch_setup_t<float>(b);
+      if (rc != TLB_OK) return rc;
+      break;
+    }
   return b->precision == 64 ? batch_step_t<double>(b, n_steps) : batch_step_t<float>(b, n_steps);
 }
 
@@ -1741,6 +1810,7 @@ void tlb_destroy_batch(tlb_batch* b) {
   if (b->table) (void)hipFree(b->table);
   if (b->tile_begin) (void)hipFree(b->tile_begin);
   delete[] b->grids;
+  delete[] b->versions;
   delete b;
 }
 

@@ -25,7 +25,10 @@ struct tlb_grid {
   int ty;                     // tile height of the stage kernel (4, 8 or 16)
   hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
   bool chunk_tried;
+  unsigned chunk_version;     // version of the grid when chunk_exec was built
   void* dft_work;  // structure-factor workspace (built on first use): row transforms and twiddles
+  double n_ref;      // reference density of FP32 storage (see stores_deviation), a float value
+  unsigned version;  // changes whenever n_ref does: stage arguments kept in graphs are stale
 };
 
 // Records `msg` as the thread's last error and returns `code`.
@@ -57,14 +60,16 @@ __host__ __device__ constexpr double wgt(int i) {
 }
 
 // Storage of the populations.  FP32 grids store each population as its deviation from the
-// rest equilibrium of unit density, f_k - w_i w_j (k = 4 i + j): the stored values are a few
-// per cent of f, so their rounding is correspondingly finer, and the small per-step increments
-// (relaxation, forcing) are not lost against O(0.1) values.  FP64 grids store f_k itself.
+// rest equilibrium of the grid's reference density n_ref, f_k - n_ref w_i w_j (k = 4 i + j;
+// n_ref is the mean density of the state loaded last, to two significant digits): the stored
+// values are a few per cent of f, so their rounding is correspondingly finer, and the small
+// per-step increments (relaxation, forcing) are not lost against O(0.1 n) values.  FP64 grids
+// store f_k itself.
 template <typename T>
 __host__ __device__ constexpr bool stores_deviation() {
   return std::is_same<T, float>::value;
 }
-// the value subtracted before storage: w_i w_j for deviation storage, else 0
+// the value subtracted before storage, per unit of n_ref: w_i w_j for deviation storage, else 0
 template <typename T>
 __host__ __device__ constexpr double rest_offset(int k) {
   return stores_deviation<T>() ? wgt(k >> 2) * wgt(k & 3) : 0.0;

@@ -87,6 +87,39 @@ def test_batch_equals_grids_stepped_alone(torch_cuda, precision):
         assert torch_cuda.equal(g.get_state()[0], h.get_state()[0])
 
 
+def test_new_reference_density_reaches_graphs_and_batches(torch_cuda):
+    """FP32 grids store deviations from the rest equilibrium of a reference density taken from
+    the loaded state.  Reloading a grid with a state of another mean density (here 20 after 1)
+    changes it after a graph of its steps or a batch holding it was built: both must pick up
+    the new stage arguments, so the grid ends bit for bit where a fresh grid ends."""
+    from paper_1904_10070_amd import TorusBatch, TorusGrid
+    p = inputs.TorusParams(1.0, 2.5, 40, 100, 0.5, 2e-3, 0.05, 0.3, 2e-4)
+    phi, n, ut, up = inputs.random_state(p, seed=21)
+    dense = (phi, 20.0 * n, ut, up)
+
+    def fresh(steps):
+        g = TorusGrid(p, precision=32)
+        g.set_state(*dense)
+        g.step(steps)
+        return g.get_state()
+
+    single = make(p, 32, seed=22)
+    single.step(64)                       # builds and replays the step graph
+    single.set_state(*dense)
+    single.step(40)
+    other = make(p, 32, seed=23)
+    member = make(p, 32, seed=24)
+    batch = TorusBatch([other, member])
+    batch.step(40)                        # builds the table and the batch graph
+    member.set_state(*dense)
+    batch.step(40)
+    ref = fresh(40)
+    torch_cuda.cuda.synchronize()
+    for g in (single, member):
+        f, ph = g.get_state()
+        assert torch_cuda.equal(f, ref[0]) and torch_cuda.equal(ph, ref[1])
+
+
 def test_weno_grids_keep_their_tile_and_stay_out_of_batches(torch_cuda):
     from paper_1904_10070_amd import TorusGrid, TorusBatch, TlbError, WENO5
     p = inputs.TorusParams(1.0, 2.5, 16, 64, 0.5, 2e-3, 0.05, 0.3, 2e-4, WENO5)

@@ -145,13 +145,15 @@ def test_adam_step_matches_reference(torch_cuda):
         p = got      # follow the GPU's weights so that differences do not accumulate
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_restrict_matches_reference(torch_cuda, precision):
+@pytest.mark.parametrize("precision, density", [(64, 1.0), (32, 1.0), (32, 20.0)])
+def test_restrict_matches_reference(torch_cuda, precision, density):
+    """(density 20: the FP32 coarse grid takes over the fine grid's reference density)"""
     from paper_1904_10070_amd import TorusGrid
     from paper_1904_10070_amd.binding import restrict
     pf = inputs.TorusParams(1.0, 2.5, 32, 80, 0.5, 2e-3, 0.05, 0.3, 2e-4)
     pc = pf.with_(n_theta=8, n_phi=20)
     f, phi = inputs.random_populations(32, 80, seed=11)
+    f = density * f
     fine, coarse = TorusGrid(pf, precision), TorusGrid(pc, precision)
     fine.set_state(phi, f=f)
     restrict(fine, coarse)

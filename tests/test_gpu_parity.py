@@ -108,6 +108,32 @@ def test_drop_workload_fp32_tolerance(torch_cuda):
         assert v <= bars[k], (k, v)
 
 
+def test_drop_workload_fp32_dense_fluid(torch_cuda):
+    """The drop workload at density 20 (the density of the paper's phase-separation runs).
+    FP32 grids store deviations from the rest equilibrium of the state's own mean density, so
+    the bars of unit density hold: against the FP64 oracle after 2000 steps, and for the mass
+    over 20,000 steps (storing deviations from unit density, the mass drifted by 1.8e-2 over
+    10^6 steps at this density)."""
+    p = inputs.drop_workload()
+    phi = inputs.drop_workload_phi(p, seed=1)
+    n, ut, up = inputs.rest_moments(p.n_theta, p.n_phi, n0=20.0)
+    og, f_ref, phi_ref = oracle_run(p, phi, n, ut, up, 2000)
+    gg, f_gpu, phi_gpu = gpu_run(p, phi, n, ut, up, 2000, precision=32)
+    mr, mg = og.moments(), moments_np(gg.moments())
+    errs = dict(f=rel_linf(f_gpu, f_ref), phi=rel_linf(phi_gpu, phi_ref),
+                n=rel_linf(mg["n"], mr["n"]), ut=rel_linf(mg["u_theta"], mr["u_theta"]),
+                up=rel_linf(mg["u_phi"], mr["u_phi"]))
+    m_exact = 20.0 * 4 * math.pi ** 2 * p.r * p.R
+    errs["mass"] = abs(gg.invariants()[0] - m_exact) / m_exact
+    gg.step(18000)
+    errs["mass_20000"] = abs(gg.invariants()[0] - m_exact) / m_exact
+    print("fp32 at density 20 vs fp64 oracle", {k: f"{v:.2e}" for k, v in errs.items()},
+          flush=True)
+    bars = dict(f=1.5e-3, phi=1e-3, n=1.5e-3, ut=3e-2, up=3e-2, mass=3e-4, mass_20000=1e-5)
+    for k, v in errs.items():
+        assert v <= bars[k], (k, v)
+
+
 def test_checkpoint_resume_is_bitwise(torch_cuda):
     p = inputs.TorusParams(1.0, 2.5, 20, 70, 0.5, 2e-3, 0.05, 0.3, 2e-4)
     phi, n, ut, up = inputs.random_state(p, seed=5)
