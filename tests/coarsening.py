@@ -3,7 +3,7 @@ tscal-ev): the domain length L_d = A_total / L_I grows with an apparent exponent
 hydrodynamics (viscous-inertial regime) and 1/3 without the convective term of the
 Cahn-Hilliard equation (diffusive regime), until the domains wrap round the tube.
 
-TEST INFRASTRUCTURE: used by test_gpu_drift.py, and run as
+TEST INFRASTRUCTURE (a study script beside the tests): run as
 `python -m tests.coarsening [hydro|diffusive] [64|32] [t_end]` from the repository root.
 
 Set-up (the paper's): R = 2.5, r = 1, N_theta x N_phi = 400 x 800, phi = uniform noise in
