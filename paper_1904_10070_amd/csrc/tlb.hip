@@ -338,6 +338,24 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 #ifndef TLB_RING64
 #define TLB_RING64 4
 #endif
+// Streaming (nontemporal) accesses for the stage outputs and the y^n loads, used on grids whose
+// state copies are far larger than the 256 MB last-level cache: there the output streams gain
+// nothing from being cached, while on grids that fit it the next stage reads them from there.
+template <bool NT, typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ T get_y0(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 template <typename T>
 struct Ring {
   static constexpr int D = sizeof(T) == 4 ? TLB_RING32 : TLB_RING64;
@@ -346,7 +364,7 @@ struct Ring {
 
 // One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
 // described by `a`, by a block of Tile<TY>::NT threads.
-template <typename T, bool VEC, int TY, bool WENO = false>
+template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, const int ty) {
 // (the body is device code: the host pass of the single-source compiler skips it; with both
 // advection variants instantiated, that pass otherwise rejects the call from the batch kernel)
@@ -435,7 +453,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const long long node_pf = (long long)qw * np + (s < np ? s : 0);
   T phin = T(0);
   if constexpr (PF)
-    if (a.has_y0) phin = a.phi0[node_pf];
+    if (a.has_y0) phin = get_y0<STREAM>(a.phi0 + node_pf);
   // moments of this node and of the ring node, both summed population by population in the
   // same order, so that a node's moments (and all that follows) do not depend on whether it
   // is inside a tile or in a neighbour's ring -- results are independent of the tile shape
@@ -468,7 +486,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
     const T* buf = slot(ic<k>{});
     if constexpr (PF)
-      if (a.has_y0) yn[k] = a.f0[k * a.plane + node_pf];
+      if (a.has_y0) yn[k] = get_y0<STREAM>(a.f0 + k * a.plane + node_pf);
     f[k] = buf[cN];
     n += f[k];
     nut += T(vel(i)) * f[k];
@@ -570,9 +588,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   if (active) {
     const T ys = phc + dt * Lphi;
     if constexpr (PF)
-      a.phiout[node] = y0 ? a0 * phin + b1 * ys : ys;
+      put<STREAM>(a.phiout + node, y0 ? a0 * phin + b1 * ys : ys);
     else
-      a.phiout[node] = y0 ? a0 * a.phi0[node] + b1 * ys : ys;
+      put<STREAM>(a.phiout + node, y0 ? a0 * a.phi0[node] + b1 * ys : ys);
   }
 
   // ---- equilibrium (eq. feq) as a cubic in xi = v.u:
@@ -618,20 +636,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     if (active) {
       T* dst = a.fout + k * a.plane + node;
       if constexpr (PF)
-        *dst = y0 ? a0 * yn[k] + b1 * ys : ys;
+        put<STREAM>(dst, y0 ? a0 * yn[k] + b1 * ys : ys);
       else
-        *dst = y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys;
+        put<STREAM>(dst, y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys);
     }
   });
 #endif
 }
 
-template <typename T, bool VEC, int TY, bool WENO = false>
+template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false>
 __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   int tx, ty;
   band_tile(tile, a.ntx, a.nty, tx, ty);
-  stage_tile<T, VEC, TY, WENO>(a, tx, ty);
+  stage_tile<T, VEC, TY, WENO, STREAM>(a, tx, ty);
 }
 
 // One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
@@ -1048,12 +1066,28 @@ bool vec_ok(int n_phi) {
 }
 
 template <typename T, bool VEC>
-const void* stage_fn_ty(int ty) {
+const void* stage_fn_ty(int ty, bool streaming) {
+  if (streaming) {  // the 16-byte-copy form only (every large grid here has n_phi % 4 == 0)
+    if constexpr (VEC) {
+      switch (ty) {
+        case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 4, false, true>);
+        case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 16, false, true>);
+        default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 8, false, true>);
+      }
+    }
+  }
   switch (ty) {
     case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 4>);
     case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 16>);
     default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 8>);
   }
+}
+
+// Grids whose three state copies (51 values per node) exceed this use streaming accesses
+constexpr double STREAMING_BYTES = 1024.0 * 1024.0 * 1024.0;
+
+bool streaming(const tlb_grid* g) {
+  return 51.0 * g->p.n_theta * (double)g->p.n_phi * (double)g->elem > STREAMING_BYTES;
 }
 
 template <typename T>
@@ -1062,7 +1096,8 @@ const void* stage_fn(const tlb_grid* g) {
     return vec_ok<T>(g->p.n_phi)
                ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true>)
                : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, true>);
-  return vec_ok<T>(g->p.n_phi) ? stage_fn_ty<T, true>(g->ty) : stage_fn_ty<T, false>(g->ty);
+  return vec_ok<T>(g->p.n_phi) ? stage_fn_ty<T, true>(g->ty, streaming(g))
+                                : stage_fn_ty<T, false>(g->ty, streaming(g));
 }
 
 template <typename T, bool VEC>

@@ -187,6 +187,30 @@ def test_spinodal_full_size_fp64_and_fp32(torch_cuda):
     assert e32f <= 1e-5 and e32p <= 1e-5
 
 
+@pytest.mark.timeout(300)
+def test_roofline_size_streaming_fp64_and_fp32(torch_cuda):
+    """2048 x 5120, whose state copies (2.1 GB in FP32, 4.3 GB in FP64) are far beyond the
+    last-level cache, so the stage kernel streams its outputs and the y^n loads past the
+    caches: 2 steps against the oracle, FP64 at 1e-12 and FP32 within single-precision
+    rounding (the launch configuration the benchmark times for this grid)."""
+    p = inputs.roofline_workload()
+    phi = inputs.spinodal_phi(p, seed=7)
+    n, ut, up = inputs.rest_moments(p.n_theta, p.n_phi)
+    og, f_ref, phi_ref = oracle_run(p, phi, n, ut, up, 2)
+    del og
+    g, f64, p64 = gpu_run(p, phi, n, ut, up, 2, precision=64)
+    g.close()
+    e64f, e64p = rel_linf(f64, f_ref), rel_linf(p64, phi_ref)
+    del f64, p64
+    g, f32, p32 = gpu_run(p, phi, n, ut, up, 2, precision=32)
+    g.close()
+    e32f, e32p = rel_linf(f32, f_ref), rel_linf(p32, phi_ref)
+    print(f"2048x5120 after 2 steps: fp64 f {e64f:.2e} phi {e64p:.2e}; "
+          f"fp32 f {e32f:.2e} phi {e32p:.2e}", flush=True)
+    assert e64f <= FP64_TOL and e64p <= FP64_TOL
+    assert e32f <= 1e-5 and e32p <= 1e-5
+
+
 def test_graph_replay_matches_plain_launches_bitwise(torch_cuda):
     """tlb_step_n replays a prebuilt graph of 32 steps; with TLB_NO_GRAPH it launches each
     kernel.  Several replays, with eager work and synchronisation between them, must give
