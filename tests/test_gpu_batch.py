@@ -130,3 +130,39 @@ def test_weno_grids_keep_their_tile_and_stay_out_of_batches(torch_cuda):
     g.set_tile_rows(8)
     with pytest.raises(TlbError):
         TorusBatch([g])
+
+
+@pytest.mark.timeout(300)
+def test_benchmark_ensemble_matches_grids_alone(torch_cuda):
+    """The ensemble the benchmark times: 64 tori of 128..512 x 256..1024 nodes (15.2 M in all,
+    FP32, seeded spinodal states, autotuned tile height).  After 40 steps (one graph replay of
+    32 steps and 8 single launches) every torus is bit for bit where it is when stepped alone."""
+    from paper_1904_10070_amd import TorusBatch, TorusGrid
+    params = inputs.ensemble_workload()
+
+    def grids():
+        out = []
+        for i, p in enumerate(params):
+            g = TorusGrid(p, precision=32)
+            g.set_state(inputs.spinodal_phi(p, seed=1000 + i),
+                        *inputs.rest_moments(p.n_theta, p.n_phi))
+            out.append(g)
+        return out
+
+    batched = grids()
+    batch = TorusBatch(batched)
+    rows = batch.autotune()
+    batch.step(40)
+    alone = grids()
+    for g in alone:
+        g.step(40)
+    torch_cuda.cuda.synchronize()
+    print(f"64 tori, {sum(p.n_theta * p.n_phi for p in params)} nodes, tile rows {rows}",
+          flush=True)
+    for i, (g, h) in enumerate(zip(alone, batched)):
+        fa, pa = g.get_state()
+        fb, pb = h.get_state()
+        assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb), i
+    batch.close()
+    for g in alone + batched:
+        g.close()
