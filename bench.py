@@ -360,7 +360,12 @@ def main():
                      "traffic": measured_traffic("spinodal512x1280_fp32"),
                      "kernel": "tlb_stage_kernel<float>",
                      "bytes_per_launch": head["bytes_per_launch"],
-                     "copy_gbs": copy_bandwidth()},
+                     "copy_gbs": copy_bandwidth(),
+                     # the same copy between two buffers of half the three state copies
+                     # each (134 MB in all, which stays in the 256 MB last-level cache, as
+                     # the working set of this grid does)
+                     "copy_gbs_working_set": copy_bandwidth(
+                         mib=max(1, int(51 * p.n_theta * p.n_phi * 4 / 2 / (1 << 20))), reps=50)},
     }
     if not args.no_extra:
         steps64 = max(10, args.steps // 2)
