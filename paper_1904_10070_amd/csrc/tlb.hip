@@ -336,7 +336,7 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 #define TLB_RING32 4
 #endif
 #ifndef TLB_RING64
-#define TLB_RING64 4
+#define TLB_RING64 6
 #endif
 // Streaming (nontemporal) accesses for the stage outputs and the y^n loads, used on grids whose
 // state copies are far larger than the 256 MB last-level cache: there the output streams gain
