@@ -267,7 +267,40 @@ def cpu_baseline(p, budget_s=15.0):
     return dict(value=p.n_theta * p.n_phi * n_more / dt, unit="node-updates/s", cores=cores,
                 kind="oracle",
                 sample=f"FP64 oracle, {n_more} steps of the {p.n_theta}x{p.n_phi} spinodal "
-                       f"workload after 1 warm-up step ({dt:.1f} s)")
+                       f"workload after 1 warm-up step ({dt:.1f} s)",
+                single_thread=cpu_single_thread(p))
+
+
+SINGLE_THREAD_SCRIPT = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import ref
+from paper_1904_10070_amd import inputs
+p = inputs.spinodal_workload(0.6)
+g = ref.RefGrid(**p.as_dict())
+g.set_state(inputs.spinodal_phi(p, seed=7), *inputs.rest_moments(p.n_theta, p.n_phi))
+g.step(1)
+t0 = time.perf_counter()
+g.step(2)
+dt = time.perf_counter() - t0
+print(json.dumps({"value": p.n_theta * p.n_phi * 2 / dt, "steps": 2, "seconds": dt}))
+"""
+
+
+def cpu_single_thread(p):
+    """The same oracle on one thread (a CPU-only child process with OMP_NUM_THREADS=1, since
+    the thread count is fixed when the oracle library loads): 2 steps after 1 warm-up step."""
+    import subprocess
+    import sys
+    assert (p.n_theta, p.n_phi) == (512, 1280), "the single-thread leg times the spinodal grid"
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SCRIPT, ROOT], env=env,
+                           capture_output=True, text=True, timeout=180)
+        return dict(json.loads(r.stdout.strip().splitlines()[-1]), unit="node-updates/s",
+                    cores=1)
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        return {"error": str(e)[:200]}
 
 
 def main():
