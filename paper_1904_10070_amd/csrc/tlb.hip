@@ -338,6 +338,15 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 #ifndef TLB_RING64
 #define TLB_RING64 6
 #endif
+// Address of a node's value in plane k: a wavefront-uniform base (row and plane, scalar
+// registers) plus the lane's 32-bit byte offset, so that the access takes the scalar-base form
+// instead of a 64-bit vector address per plane.
+template <typename P>
+__device__ __forceinline__ P* at_node(P* base, long long uniform_elems, unsigned lane_bytes) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base + uniform_elems) + lane_bytes);
+}
+
 // Streaming (nontemporal) accesses for the stage outputs and the y^n loads, used on grids whose
 // state copies are far larger than the 256 MB last-level cache: there the output streams gain
 // nothing from being cached, while on grids that fit it the next stage reads them from there.
@@ -363,8 +372,11 @@ struct Ring {
 };
 
 // One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
-// described by `a`, by a block of Tile<TY>::NT threads.
-template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false>
+// described by `a`, by a block of Tile<TY>::NT threads.  GENREF: the FP32 storage reference
+// density is read from the arguments; otherwise it is the constant 1 (every grid near unit
+// density), whose products the compiler folds away.
+template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false,
+          bool GENREF = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, const int ty) {
 // (the body is device code: the host pass of the single-source compiler skips it; with both
 // advection variants instantiated, that pass otherwise rejects the call from the batch kernel)
@@ -450,10 +462,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   // y^n at this node for the Runge-Kutta combine, loaded during the population loop
   constexpr bool PF = Ring<T>::PREFETCH;
   T yn[PF ? 16 : 1];
-  const long long node_pf = (long long)qw * np + (s < np ? s : 0);
+  const long long row0 = (long long)qw * np;  // wavefront-uniform
+  const unsigned lane_bytes = (unsigned)(s < np ? s : 0) * (unsigned)sizeof(T);
   T phin = T(0);
   if constexpr (PF)
-    if (a.has_y0) phin = get_y0<STREAM>(a.phi0 + node_pf);
+    if (a.has_y0) phin = get_y0<STREAM>(at_node(a.phi0, row0, lane_bytes));
   // moments of this node and of the ring node, both summed population by population in the
   // same order, so that a node's moments (and all that follows) do not depend on whether it
   // is inside a tile or in a neighbour's ring -- results are independent of the tile shape
@@ -462,7 +475,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const int cN = (ly + HY) * LXT + lx + CX;  // this node in the population tile
   const int cR = (ry + HY) * LXT + rx + CX;  // the ring node
   const T inv_Jdph = rc.inv_Jdph;
-  const T n_ref = a.c.n_ref;
+  T n_ref = T(1);
+  if constexpr (GENREF) n_ref = a.c.n_ref;
   // WENO: J of rows q-3..q+3 (wavefront-uniform scalar loads) and 1 / (r J dtheta)
   T Jnb[7];
   T inv_rJdth = T(0);
@@ -486,7 +500,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
       cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
     const T* buf = slot(ic<k>{});
     if constexpr (PF)
-      if (a.has_y0) yn[k] = get_y0<STREAM>(a.f0 + k * a.plane + node_pf);
+      if (a.has_y0) yn[k] = get_y0<STREAM>(at_node(a.f0, k * a.plane + row0, lane_bytes));
     f[k] = buf[cN];
     n += f[k];
     nut += T(vel(i)) * f[k];
@@ -582,15 +596,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
             (sPp[cp + 1] - sPp[cp - 1]) * rc.inv_2Jdph;
   }
 
-  const long long node = (long long)qw * np + (s < np ? s : 0);
+
   const T dt = a.c.dt, a0 = a.a0, b1 = a.b1;
   const bool y0 = a.has_y0;
   if (active) {
     const T ys = phc + dt * Lphi;
     if constexpr (PF)
-      put<STREAM>(a.phiout + node, y0 ? a0 * phin + b1 * ys : ys);
+      put<STREAM>(at_node(a.phiout, row0, lane_bytes), y0 ? a0 * phin + b1 * ys : ys);
     else
-      put<STREAM>(a.phiout + node, y0 ? a0 * a.phi0[node] + b1 * ys : ys);
+      put<STREAM>(at_node(a.phiout, row0, lane_bytes),
+                  y0 ? a0 * *at_node(a.phi0, row0, lane_bytes) + b1 * ys : ys);
   }
 
   // ---- equilibrium (eq. feq) as a cubic in xi = v.u:
@@ -634,29 +649,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     const T L = adv[k] + (G * T(vel(j) * vel(j)) - Fth) * dvt - dvp + relax * a.c.inv_tau;
     const T ys = f[k] + dt * L;
     if (active) {
-      T* dst = a.fout + k * a.plane + node;
+      T* dst = at_node(a.fout, k * a.plane + row0, lane_bytes);
       if constexpr (PF)
         put<STREAM>(dst, y0 ? a0 * yn[k] + b1 * ys : ys);
       else
-        put<STREAM>(dst, y0 ? a0 * a.f0[k * a.plane + node] + b1 * ys : ys);
+        put<STREAM>(dst, y0 ? a0 * *at_node(a.f0, k * a.plane + row0, lane_bytes) + b1 * ys : ys);
     }
   });
 #endif
 }
 
-template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false>
+template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false,
+          bool GENREF = false>
 __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   int tx, ty;
   band_tile(tile, a.ntx, a.nty, tx, ty);
-  stage_tile<T, VEC, TY, WENO, STREAM>(a, tx, ty);
+  stage_tile<T, VEC, TY, WENO, STREAM, GENREF>(a, tx, ty);
 }
 
 // One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
 // the stage arguments of grid g; tile_begin[g] is the first tile of grid g in the concatenated
 // tile order (tile_begin[n] = total).  XCD x owns a contiguous range of that order, which its
 // gridDim.x / 8 resident blocks walk with a stride, tile by tile.
-template <typename T, bool VEC, int TY>
+template <typename T, bool VEC, int TY, bool GENREF = false>
 __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
     const StageArgs<T>* __restrict__ table, const int* __restrict__ tile_begin, int n, int stage) {
   const int total = tile_begin[n];
@@ -674,7 +690,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
     const StageArgs<T> a = table[3 * lo + stage - 1];
     int tx, ty;
     band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
-    stage_tile<T, VEC, TY, false>(a, tx, ty);
+    stage_tile<T, VEC, TY, false, false, GENREF>(a, tx, ty);
     __syncthreads();  // the next tile reuses the LDS tiles
   }
 }
@@ -1065,22 +1081,28 @@ bool vec_ok(int n_phi) {
   return n_phi % (16 / (int)sizeof(T)) == 0;
 }
 
-template <typename T, bool VEC>
+template <typename T, bool VEC, bool GENREF>
 const void* stage_fn_ty(int ty, bool streaming) {
   if (streaming) {  // the 16-byte-copy form only (every large grid here has n_phi % 4 == 0)
     if constexpr (VEC) {
       switch (ty) {
-        case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 4, false, true>);
-        case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 16, false, true>);
-        default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 8, false, true>);
+        case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 4, false, true, GENREF>);
+        case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 16, false, true, GENREF>);
+        default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, 8, false, true, GENREF>);
       }
     }
   }
   switch (ty) {
-    case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 4>);
-    case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 16>);
-    default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 8>);
+    case 4: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 4, false, false, GENREF>);
+    case 16: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 16, false, false, GENREF>);
+    default: return reinterpret_cast<const void*>(&tlb_stage_kernel<T, VEC, 8, false, false, GENREF>);
   }
+}
+
+// FP32 grids whose reference density is not 1 need the kernels that read it
+template <typename T>
+bool general_reference(const tlb_grid* g) {
+  return stores_deviation<T>() && g->n_ref != 1.0;
 }
 
 // Grids whose three state copies (51 values per node) exceed this use streaming accesses
@@ -1092,21 +1114,37 @@ bool streaming(const tlb_grid* g) {
 
 template <typename T>
 const void* stage_fn(const tlb_grid* g) {
-  if (g->p.flags & TLB_WENO5)  // the WENO variant exists for the default tile height only
-    return vec_ok<T>(g->p.n_phi)
-               ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true>)
+  const bool vec = vec_ok<T>(g->p.n_phi), gen = general_reference<T>(g);
+  if (g->p.flags & TLB_WENO5) {  // the WENO variant exists for the default tile height only
+    if (gen)
+      return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true, false, true>)
+                 : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, true, false, true>);
+    return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true>)
                : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, true>);
-  return vec_ok<T>(g->p.n_phi) ? stage_fn_ty<T, true>(g->ty, streaming(g))
-                                : stage_fn_ty<T, false>(g->ty, streaming(g));
+  }
+  if (gen)
+    return vec ? stage_fn_ty<T, true, true>(g->ty, streaming(g))
+               : stage_fn_ty<T, false, true>(g->ty, streaming(g));
+  return vec ? stage_fn_ty<T, true, false>(g->ty, streaming(g))
+             : stage_fn_ty<T, false, false>(g->ty, streaming(g));
 }
 
-template <typename T, bool VEC>
+template <typename T, bool VEC, bool GENREF>
 const void* batch_fn_ty(int ty) {
   switch (ty) {
-    case 4: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 4>);
-    case 16: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 16>);
-    default: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 8>);
+    case 4: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 4, GENREF>);
+    case 16: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 16, GENREF>);
+    default: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 8, GENREF>);
   }
+}
+
+// the batch kernel for the batch's current grids (the general-reference form if any needs it)
+template <typename T>
+const void* batch_fn(const tlb_batch* b) {
+  bool gen = false;
+  for (int i = 0; i < b->n; ++i) gen = gen || general_reference<T>(b->grids[i]);
+  if (gen) return b->vec ? batch_fn_ty<T, true, true>(b->ty) : batch_fn_ty<T, false, true>(b->ty);
+  return b->vec ? batch_fn_ty<T, true, false>(b->ty) : batch_fn_ty<T, false, false>(b->ty);
 }
 
 int stage_blocks(const tlb_grid* g) {
@@ -1300,7 +1338,7 @@ int32_t batch_setup_t(tlb_batch* b) {
   std::free(tab);
   std::free(tb);
   if (e != hipSuccess) return fail(TLB_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
-  const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+  const void* fn = batch_fn<T>(b);
   int dev = 0, cus = 0, per_cu = 0;
   TLB_HIP_CHECK(hipGetDevice(&dev));
   TLB_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1315,7 +1353,7 @@ int32_t batch_setup_t(tlb_batch* b) {
 
 template <typename T>
 int32_t batch_launch_t(tlb_batch* b, int stage) {
-  const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+  const void* fn = batch_fn<T>(b);
   const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
   const int* tile_begin = b->tile_begin;
   int n = b->n;
@@ -1328,7 +1366,7 @@ template <typename T>
 int32_t batch_step_t(tlb_batch* b, int64_t n) {
   if (n >= GRAPH_CHUNK && !b->chunk_tried) {
     b->chunk_tried = true;
-    const void* fn = b->vec ? batch_fn_ty<T, true>(b->ty) : batch_fn_ty<T, false>(b->ty);
+    const void* fn = batch_fn<T>(b);
     const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
     const int* tile_begin = b->tile_begin;
     int nn = b->n;
