@@ -194,6 +194,11 @@ struct StageArgs {
 };
 
 __device__ __forceinline__ int wrapi(int x, int n) {
+  // the indices wrapped here are almost always in range or one period off; only grids smaller
+  // than a halo need the division
+  if (x >= 0 && x < n) return x;
+  if (x < 0 && x >= -n) return x + n;
+  if (x >= n && x < 2 * n) return x - n;
   int m = x % n;
   return m < 0 ? m + n : m;
 }
