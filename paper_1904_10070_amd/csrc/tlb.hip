@@ -343,6 +343,16 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 #ifndef TLB_RING64
 #define TLB_RING64 6
 #endif
+// 1 / x: the hardware reciprocal (1 ulp) in FP32, where the correctly rounded division would
+// cost about ten instructions of an issue-bound kernel; a correctly rounded division in FP64.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  if constexpr (std::is_same<T, float>::value)
+    return __builtin_amdgcn_rcpf(x);
+  else
+    return T(1) / x;
+}
+
 // Address of a node's value in plane k: a wavefront-uniform base (row and plane, scalar
 // registers) plus the lane's 32-bit byte offset, so that the access takes the scalar-base form
 // instead of a 64-bit vector address per plane.
@@ -573,14 +583,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     n += n_ref;
     rn += n_ref;
   }
-  const T inv_n = T(1) / n;
+  const T inv_n = recip(n);
   const T ut = nut * inv_n, up = nup * inv_n;
   const T phc = sPhi[(ly + 2) * LXT + lx + CX];
   sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
   sPp[ly * (TX + 2) + lx + 1] = up * phc;
   if (ring) {
     const T phr = sPhi[(ry + 2) * LXT + rx + CX];
-    const T inv_rn = T(1) / rn;
+    const T inv_rn = recip(rn);
     if (ry < 0 || ry >= TY) sPt[(ry + 1) * TX + rx] = rrc.J * (rut * inv_rn) * phr;
     else sPp[ry * (TX + 2) + rx + 1] = (rup * inv_rn) * phr;
   }
