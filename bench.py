@@ -19,7 +19,6 @@ launch time, measured with HIP events on the stream the kernels run on.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time

@@ -29,7 +29,6 @@ factor J = R + r cos(theta) and the equilibrium come from section II, eqs. torus
 
 Parameters are one flat FP32 vector, layer by layer: W[c_out][tap][c_in] then b[c_out].
 """
-import math
 
 import numpy as np
 

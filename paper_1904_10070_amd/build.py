@@ -2,7 +2,6 @@
 paper_1904_10070_amd/libtlb.so (in-tree)."""
 import os
 import subprocess
-import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)

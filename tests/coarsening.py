@@ -12,7 +12,6 @@ tau = M = 2.5e-3, dt = 5e-4.  L_d and the structure-factor length L_S are taken 
 logarithmically spaced times; the exponent is the least-squares slope of log L against log t
 over a window.
 """
-import math
 import sys
 
 import numpy as np

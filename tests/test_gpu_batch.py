@@ -6,7 +6,6 @@ batch of tori of different sizes, aspect ratios and time steps gives the same st
 stepping it alone (which the parity tests tie to the oracle).  The bit-exact tile-seam check
 also catches halo races between the LDS tiles.
 """
-import math
 
 import numpy as np
 import pytest

@@ -9,7 +9,6 @@ the hidden values.  Propagated to the output that is a relative L2 difference of
 the bars are 1e-3 (L2) and 1e-2 (L-infinity, relative to the largest value).  Operations
 without bfloat16 (restriction, moments, correction) are held to FP64 / FP32 rounding.
 """
-import math
 
 import numpy as np
 import pytest

@@ -13,10 +13,8 @@
     discrete right-hand side must vanish at fifth order -- a sign or factor error in the
     connection term would leave an O(1) residual.
 """
-import math
 
 import numpy as np
-import pytest
 
 from oracle import ref
 from paper_1904_10070_amd import inputs
