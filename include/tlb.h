@@ -22,6 +22,11 @@
  * far less of the small per-step increments (it otherwise biases the mass by about 1e-2 over
  * 1e6 steps).  tlb_set_state and tlb_get_state convert; a caller reading an FP32 grid's f
  * buffers directly sees deviations.  Precision 64 stores f_k itself.
+ * Arithmetic in precision 32 differs from precision 64 in two places beyond the element type:
+ * 1/n is the hardware reciprocal (1 ulp), and the Runge-Kutta combination of phi is taken as
+ * phi^n + b (phi_s - phi^n + dt L) rather than (1 - b) phi^n + b (phi_s + dt L) (the same
+ * value; it avoids a rounding bias of the sum of phi where phi is near +-1).  Grids whose three
+ * state copies exceed 1 GiB write their stage outputs with streaming (nontemporal) stores.
  *
  * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
  * buffers); they must outlive the grid handle.  The library owns only its per-row geometry
