@@ -29,47 +29,101 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 VALUES_PER_NODE_STEP = 136
+REPS = 5            # timed repetitions of every measurement; the median is reported
+GRAPH_CHUNK = 32    # the library replays graphs of 32 time steps
 
 
 def algorithmic_bytes_per_node_step(precision):
     return VALUES_PER_NODE_STEP * (4 if precision == 32 else 8)
 
 
-def time_steps(grid, steps, warmup):
-    """Average time per step (s) over `steps` steps after `warmup` untimed ones."""
+def spread(ts):
+    """median, min, max and (max - min) / median of a list of times."""
+    xs = sorted(ts)
+    med = xs[len(xs) // 2] if len(xs) % 2 else 0.5 * (xs[len(xs) // 2 - 1] + xs[len(xs) // 2])
+    return dict(median=med, min=xs[0], max=xs[-1], spread=(xs[-1] - xs[0]) / med)
+
+
+def event_reps(run, stream, reps=REPS):
+    """Seconds of each of `reps` calls of run(), timed with HIP events recorded on `stream`
+    (the stream the kernels are launched on), with a synchronisation on both sides."""
     import torch
-    grid.step(warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(grid.stream):
-        start.record(grid.stream)
-        grid.step(steps)
-        stop.record(grid.stream)
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) * 1e-3 / steps
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        run()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        out.append(start.elapsed_time(stop) * 1e-3)
+    return out
 
 
-def gpu_leg(p, precision, steps, warmup, seed=7, phi=None):
+def graph_steps(t_step, seconds):
+    """A step count for a timed repetition of about `seconds`: a multiple of the graph chunk,
+    at least two chunks, so that every step is a graph replay."""
+    n = max(2 * GRAPH_CHUNK, int(seconds / max(t_step, 1e-9)))
+    return (n + GRAPH_CHUNK - 1) // GRAPH_CHUNK * GRAPH_CHUNK
+
+
+def new_grid(p, precision, seed=7, phi=None):
     from paper_1904_10070_amd import TorusGrid, inputs
     g = TorusGrid(p, precision=precision)
     phi = inputs.spinodal_phi(p, seed=seed) if phi is None else phi
     g.set_state(phi, *inputs.rest_moments(p.n_theta, p.n_phi))
-    t_step = time_steps(g, steps, warmup)
-    mass, phisum, bad = g.invariants()
+    return g
+
+
+def leg_result(p, precision, ts_per_step, steps):
+    """node-updates/s and the roofline figures of a median time per step."""
+    st = spread(ts_per_step)
+    t_step = st["median"]
     nodes = p.n_theta * p.n_phi
-    nups = nodes / t_step
     bytes_launch = algorithmic_bytes_per_node_step(precision) * nodes / 3.0
     achieved = bytes_launch / (t_step / 3.0) / 1e9
+    return dict(nups=nodes / t_step, t_step=t_step, achieved_gbs=achieved,
+                bytes_per_launch=bytes_launch, steps=steps,
+                timing={"reps": len(ts_per_step), "steps_per_rep": steps,
+                        "ms_per_step_median": t_step * 1e3, "ms_per_step_min": st["min"] * 1e3,
+                        "ms_per_step_max": st["max"] * 1e3, "spread": st["spread"]})
+
+
+def gpu_leg(p, precision, steps, warmup, seed=7, phi=None):
+    """`warmup` untimed steps, then REPS timed repetitions of exactly `steps` steps."""
+    g = new_grid(p, precision, seed, phi)
+    g.step(warmup)
+    ts = [t / steps for t in event_reps(lambda: g.step(steps), g.stream)]
+    bad = g.invariants()[2]
     g.close()
-    return dict(nups=nups, t_step=t_step, achieved_gbs=achieved, nonfinite=bad,
-                bytes_per_launch=bytes_launch)
+    return dict(leg_result(p, precision, ts, steps), nonfinite=bad)
 
 
-def ensemble_leg(steps, warmup):
+def graph_leg(p, precision, seconds=1.0, seed=7, phi=None, grid=None):
+    """REPS repetitions of about `seconds` each, every step a graph replay (two warm-up chunks
+    build the graph first)."""
+    g = grid if grid is not None else new_grid(p, precision, seed, phi)
+    g.step(2 * GRAPH_CHUNK)
+    probe = event_reps(lambda: g.step(2 * GRAPH_CHUNK), g.stream, reps=1)[0] / (2 * GRAPH_CHUNK)
+    steps = graph_steps(probe, seconds)
+    ts = [t / steps for t in event_reps(lambda: g.step(steps), g.stream)]
+    bad = g.invariants()[2]
+    if grid is None:
+        g.close()
+    return dict(leg_result(p, precision, ts, steps), nonfinite=bad)
+
+
+def leg_json(d, **extra):
+    return dict({"value": d["nups"], "unit": "node-updates/s", "ms_per_step": d["t_step"] * 1e3,
+                 "steps": d["steps"], "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
+                 "achieved_gbs": d["achieved_gbs"], "timing": d["timing"]}, **extra)
+
+
+def ensemble_leg(seconds=0.5):
     """64 tori (inputs.ensemble_workload) in FP32: one fused launch per stage for the whole
-    ensemble (autotuned tile height) against the same grids stepped one after another."""
-    import torch
+    ensemble (autotuned tile height) against the same grids stepped one after another, both
+    graph-replayed (step counts a multiple of the 32-step chunk), REPS repetitions each."""
     from paper_1904_10070_amd import TorusBatch, TorusGrid, inputs
     params = inputs.ensemble_workload()
     grids = []
@@ -80,84 +134,98 @@ def ensemble_leg(steps, warmup):
     nodes = sum(p.n_theta * p.n_phi for p in params)
     batch = TorusBatch(grids)
     rows = batch.autotune()
+    stream = grids[0].stream
+    batch.step(2 * GRAPH_CHUNK)
+    probe = event_reps(lambda: batch.step(2 * GRAPH_CHUNK), stream, reps=1)[0] / (2 * GRAPH_CHUNK)
+    steps = graph_steps(probe, seconds)
+    tb = spread([t / steps for t in event_reps(lambda: batch.step(steps), stream)])
 
-    def timed(fn):
-        fn(warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn(steps)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
-
-    t_batch = timed(batch.step)
-    t_alone = timed(lambda k: [g.step(k) for g in grids])
+    def alone():
+        for g in grids:
+            g.step(steps)
+    alone_warm = [g.step(2 * GRAPH_CHUNK) for g in grids]
+    del alone_warm
+    ta = spread([t / steps for t in event_reps(alone, stream)])
     batch.close()
     for g in grids:
         g.close()
+    t_batch, t_alone = tb["median"], ta["median"]
+    achieved = 544.0 * nodes / t_batch / 1e9
     return {"value": nodes / t_batch, "unit": "node-updates/s", "tori": len(params),
             "nodes": nodes, "ms_per_step": t_batch * 1e3, "tile_rows": rows,
+            "state_bytes": 51 * 4 * nodes, "streaming": 51 * 4 * nodes > (1 << 30),
+            "roofline_frac": achieved / HBM_PEAK_GBS, "achieved_gbs": achieved,
             "separate_runs_value": nodes / t_alone, "speedup_vs_separate": t_alone / t_batch,
-            "steps": steps}
+            "steps": steps, "graph_replayed": True,
+            "timing": {"reps": REPS, "batch_spread": tb["spread"], "separate_spread": ta["spread"]}}
 
 
-def learned_leg(t_fine_step, steps=2000, seed=7, t_start=20.0, t_end=30.0, every_t=2.0):
+def learned_leg(t_fine_step, steps=2048, seeds=(7, 9, 10), t_start=20.0, t_end=30.0,
+                every_t=2.0):
     """The learned coarse step (128 x 320, 4x time step, weights trained by train_coarse.py)
-    on a held-out seed: the fine FP32 solver runs the spinodal workload to t_start, hands its
-    state to a learned and a plain coarse grid, and judges both up to t_end by the coarsening
-    lengths of the restricted fine state (structure-factor L_S and L_d = A_total / L_I).  Speed:
-    GPU time per unit of simulated time of the learned and plain coarse steps against the fine
-    FP32 step."""
-    import torch
-    from paper_1904_10070_amd import TorusGrid, inputs, learn as L, train_coarse
+    on held-out seeds: for each, the fine FP32 solver runs the spinodal workload to t_start,
+    hands its state to a learned and a plain coarse grid, and judges both up to t_end by the
+    coarsening lengths of the restricted fine state (structure-factor L_S and
+    L_d = A_total / L_I); the largest errors over the seeds are reported.  Speed: GPU time per
+    unit of simulated time of the learned and plain coarse steps (graph-replayed) against the
+    fine FP32 step (graph-replayed, `t_fine_step`)."""
+    from paper_1904_10070_amd import inputs, learn as L, train_coarse
     from paper_1904_10070_amd.binding import learned_step
     params, meta = train_coarse.load(0.6)
     net = train_coarse.network_from(meta, params)
     pf = inputs.spinodal_workload(0.6)
     pc = L.coarse_params(pf)
-    rows = L.evaluate(pf, net, seed, t_start, t_end, every_t, progress=None)
-    err = [abs(r["L_learned"] - r["L_judge"]) / r["L_judge"] for r in rows]
-    err_p = [abs(r["L_plain"] - r["L_judge"]) / r["L_judge"] for r in rows]
-    errs = [abs(r["LS_learned"] - r["LS_judge"]) / r["LS_judge"] for r in rows]
-    errs_p = [abs(r["LS_plain"] - r["LS_judge"]) / r["LS_judge"] for r in rows]
+    per_seed = {}
+    rows7 = None
+    for seed in seeds:
+        rows = L.evaluate(pf, net, seed, t_start, t_end, every_t, progress=None)
+        if rows7 is None:
+            rows7 = rows
+        rel = lambda a, b: [abs(r[a] - r[b]) / r[b] for r in rows]  # noqa: E731
+        per_seed[str(seed)] = {"L_S_error_max": max(rel("LS_learned", "LS_judge")),
+                               "L_d_error_max": max(rel("L_learned", "L_judge")),
+                               "L_S_error_max_plain_coarse": max(rel("LS_plain", "LS_judge")),
+                               "L_d_error_max_plain_coarse": max(rel("L_plain", "L_judge")),
+                               "phi_l2_end": rows[-1]["phi_l2_learned"],
+                               "phi_l2_end_plain_coarse": rows[-1]["phi_l2_plain"]}
 
     def per_step(stepper):
         g = L.coarse_grid(pc, precision=32)
-        g.set_state(inputs.spinodal_phi(pc, seed=seed), *inputs.rest_moments(pc.n_theta, pc.n_phi))
-        stepper(g, 64)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(g.stream)
-        stepper(g, steps)
-        stop.record(g.stream)
-        torch.cuda.synchronize()
+        g.set_state(inputs.spinodal_phi(pc, seed=seeds[0]), *inputs.rest_moments(pc.n_theta, pc.n_phi))
+        stepper(g, 2 * GRAPH_CHUNK)
+        ts = [t / steps for t in event_reps(lambda: stepper(g, steps), g.stream)]
         g.close()
-        return start.elapsed_time(stop) * 1e-3 / steps
+        return spread(ts)["median"]
 
     t_learned = per_step(lambda g, n: learned_step(g, net, n))
     t_plain = per_step(lambda g, n: g.step(n))
     fine_per_t = t_fine_step / pf.dt
+    worst = lambda k: max(v[k] for v in per_seed.values())  # noqa: E731
     return {"workload": f"spinodal {pf.n_theta}x{pf.n_phi} (tau=0.6) -> learned coarse "
                         f"{pc.n_theta}x{pc.n_phi}, dt x{round(pc.dt / pf.dt)}; hand-over at "
-                        f"t={t_start:g} from held-out seed {seed}, judged to t={t_end:g}",
-            "L_S_error_max": max(errs), "L_S_error_max_plain_coarse": max(errs_p),
-            "L_d_error_max": max(err), "L_d_error_max_plain_coarse": max(err_p),
-            "phi_l2_end": rows[-1]["phi_l2_learned"], "phi_l2_end_plain_coarse": rows[-1]["phi_l2_plain"],
+                        f"t={t_start:g} from held-out seeds {list(seeds)}, judged to t={t_end:g}",
+            "L_S_error_max": worst("L_S_error_max"), "L_d_error_max": worst("L_d_error_max"),
+            "L_S_error_max_plain_coarse": worst("L_S_error_max_plain_coarse"),
+            "L_d_error_max_plain_coarse": worst("L_d_error_max_plain_coarse"),
+            "per_seed": per_seed,
             "speedup_vs_fine_fp32": fine_per_t / (t_learned / pc.dt),
             "speedup_plain_coarse": fine_per_t / (t_plain / pc.dt),
             "ms_per_learned_step": t_learned * 1e3, "ms_per_plain_coarse_step": t_plain * 1e3,
-            "ms_per_fine_step": t_fine_step * 1e3, "steps_timed": steps,
-            "rows": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()}
-                     for r in rows],
-            "training": {"samples": meta["samples"], "data_s": meta["data_seconds"],
-                         "train_s": meta["train_seconds"],
-                         "validation_seed": meta["validation"]["seed"],
-                         "validation_L_error": meta["validation"]["largest_L_error"]}}
+            "ms_per_fine_step": t_fine_step * 1e3, "steps_timed": steps, "graph_replayed": True,
+            "rows_seed_%d" % seeds[0]: [{k: (round(v, 5) if isinstance(v, float) else v)
+                                        for k, v in r.items()} for r in rows7],
+            "training_record": {"note": "copied from the weights' metadata (written by "
+                                        "train_coarse.py when the weights were trained); not "
+                                        "measured in this run",
+                                "samples": meta["samples"], "data_s": meta["data_seconds"],
+                                "train_s": meta["train_seconds"],
+                                "validation_seed": meta["validation"]["seed"],
+                                "validation_L_error": meta["validation"]["largest_L_error"]}}
 
 
-def learned_step_timing(steps=2000):
+def learned_step_timing(steps=2048):
     """GPU time per learned and per plain coarse step on the 128 x 320 grid (profiling runs)."""
-    import torch
-    from paper_1904_10070_amd import TorusGrid, inputs, learn as L, train_coarse
+    from paper_1904_10070_amd import inputs, learn as L, train_coarse
     from paper_1904_10070_amd.binding import learned_step
     params, meta = train_coarse.load(0.6)
     net = train_coarse.network_from(meta, params)
@@ -168,14 +236,9 @@ def learned_step_timing(steps=2000):
         g = L.coarse_grid(pc, precision=32)
         out[f"tile_rows_{name}"] = g.tile_rows
         g.set_state(inputs.spinodal_phi(pc, seed=7), *inputs.rest_moments(pc.n_theta, pc.n_phi))
-        stepper(g, 64)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(g.stream)
-        stepper(g, steps)
-        stop.record(g.stream)
-        torch.cuda.synchronize()
-        out[f"ms_per_{name}_step"] = start.elapsed_time(stop) / steps
+        stepper(g, 2 * GRAPH_CHUNK)
+        ts = [t / steps for t in event_reps(lambda: stepper(g, steps), g.stream)]
+        out[f"ms_per_{name}_step"] = spread(ts)["median"] * 1e3
         g.close()
     return out
 
@@ -231,26 +294,85 @@ def measured_traffic(key):
     return rec.get("traffic_bytes_per_launch", {}).get(key)
 
 
+def stream_ceiling(gib=2.0, reps=20):
+    """The project's HBM streaming kernels (tlb_hbm_stream) on buffers of `gib` GiB each:
+    copy (1 read : 1 write), add (2 : 1) and read-only rates, median of `reps` calls after one
+    untimed call, each timed with HIP events on the current stream.  `stage_mix_gbs` is the
+    rate of the stage kernel's traffic mix at these rates: stage 1 moves 34 values at 1 : 1 and
+    stages 2 and 3 51 values each at 2 : 1 per node and step."""
+    import torch
+    from paper_1904_10070_amd.binding import hbm_stream, STREAM_COPY, STREAM_ADD, STREAM_READ
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.ones(n, dtype=torch.float32, device="cuda")
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    parts = torch.empty(4 * 8192, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, mode, a, b, c in (("copy", STREAM_COPY, x, None, z), ("add", STREAM_ADD, x, y, z),
+                                ("read", STREAM_READ, x, None, parts)):
+        moved = hbm_stream(mode, a, b, c)
+        ts = event_reps(lambda: hbm_stream(mode, a, b, c), stream, reps=reps)
+        out[name + "_gbs"] = moved / spread(ts)["median"] / 1e9
+    del x, y, z
+    torch.cuda.empty_cache()
+    t_mix = 34.0 / out["copy_gbs"] + 2 * 51.0 / out["add_gbs"]
+    out["stage_mix_gbs"] = (34.0 + 2 * 51.0) / t_mix
+    out["buffer_gib"] = gib
+    out["kernel"] = "tlb_stream_kernel (include/tlb_stream.h), 16 B per lane, nontemporal"
+    return out
+
+
 def copy_bandwidth(mib=1024, reps=20):
-    """Read+write bandwidth of a plain device-to-device copy (torch), for context: the
-    practical ceiling of a streaming kernel on this GPU, next to the 8 TB/s nominal peak."""
+    """Read+write bandwidth of a plain device-to-device copy (torch) of `mib` MiB, for context
+    next to the project's own streaming kernels."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    stop.record()
-    torch.cuda.synchronize()
-    return 8.0 * n * reps / (start.elapsed_time(stop) * 1e-3) / 1e9
+    ts = event_reps(lambda: dst.copy_(src), torch.cuda.current_stream(), reps=reps)
+    return 8.0 * n / spread(ts)["median"] / 1e9
 
 
-def cpu_baseline(p, budget_s=15.0):
-    """The FP64 oracle on the host cores: a bounded number of steps of the same workload."""
+CPU_SCRIPT = """
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import ref
+from paper_1904_10070_amd import inputs
+p = inputs.drop_workload()
+g = ref.RefGrid(**p.as_dict())
+g.set_state(inputs.drop_workload_phi(p, seed=1), *inputs.rest_moments(p.n_theta, p.n_phi))
+t0 = time.perf_counter()
+g.step(2000)
+dt = time.perf_counter() - t0
+print(json.dumps({"value": p.n_theta * p.n_phi * 2000 / dt, "steps": 2000, "seconds": dt,
+                  "threads": int(os.environ.get("OMP_NUM_THREADS", "0"))}))
+"""
+
+
+def cpu_config1(threads):
+    """The FP64 oracle on the whole 64 x 160 drop workload (2000 steps), in a CPU-only child
+    process with OMP_NUM_THREADS = threads (the thread count is fixed when the oracle loads)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), HIP_VISIBLE_DEVICES="")
+    try:
+        r = subprocess.run([sys.executable, "-c", CPU_SCRIPT, ROOT], env=env,
+                           capture_output=True, text=True, timeout=300)
+        return dict(json.loads(r.stdout.strip().splitlines()[-1]), unit="node-updates/s",
+                    cores=threads, workload="drop 64x160 FP64, 2000 steps (whole workload)")
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        return {"error": str(e)[:200], "cores": threads}
+
+
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(p, budget_s=12.0):
+    """The FP64 oracle on the host cores: a bounded sample of the headline workload (a number
+    of steps of about budget_s seconds after one warm-up step), plus the whole 64 x 160 drop
+    workload on all threads and on one."""
     from oracle import ref
     from paper_1904_10070_amd import inputs
     g = ref.RefGrid(**p.as_dict())
@@ -262,44 +384,13 @@ def cpu_baseline(p, budget_s=15.0):
     t0 = time.perf_counter()
     g.step(n_more)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=p.n_theta * p.n_phi * n_more / dt, unit="node-updates/s", cores=cores,
+    g.close()
+    threads = host_threads()
+    return dict(value=p.n_theta * p.n_phi * n_more / dt, unit="node-updates/s", cores=threads,
                 kind="oracle",
                 sample=f"FP64 oracle, {n_more} steps of the {p.n_theta}x{p.n_phi} spinodal "
-                       f"workload after 1 warm-up step ({dt:.1f} s)",
-                single_thread=cpu_single_thread(p))
-
-
-SINGLE_THREAD_SCRIPT = """
-import json, sys, time
-sys.path.insert(0, sys.argv[1])
-from oracle import ref
-from paper_1904_10070_amd import inputs
-p = inputs.spinodal_workload(0.6)
-g = ref.RefGrid(**p.as_dict())
-g.set_state(inputs.spinodal_phi(p, seed=7), *inputs.rest_moments(p.n_theta, p.n_phi))
-g.step(1)
-t0 = time.perf_counter()
-g.step(2)
-dt = time.perf_counter() - t0
-print(json.dumps({"value": p.n_theta * p.n_phi * 2 / dt, "steps": 2, "seconds": dt}))
-"""
-
-
-def cpu_single_thread(p):
-    """The same oracle on one thread (a CPU-only child process with OMP_NUM_THREADS=1, since
-    the thread count is fixed when the oracle library loads): 2 steps after 1 warm-up step."""
-    import subprocess
-    import sys
-    assert (p.n_theta, p.n_phi) == (512, 1280), "the single-thread leg times the spinodal grid"
-    env = dict(os.environ, OMP_NUM_THREADS="1")
-    try:
-        r = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SCRIPT, ROOT], env=env,
-                           capture_output=True, text=True, timeout=180)
-        return dict(json.loads(r.stdout.strip().splitlines()[-1]), unit="node-updates/s",
-                    cores=1)
-    except (subprocess.SubprocessError, ValueError, IndexError) as e:
-        return {"error": str(e)[:200]}
+                       f"workload after 1 warm-up step ({dt:.1f} s), {threads} threads",
+                config1_all_threads=cpu_config1(threads), config1_one_thread=cpu_config1(1))
 
 
 def main():
@@ -311,11 +402,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline FP32 leg")
     ap.add_argument("--only", choices=["spinodal32", "spinodal64", "roofline32", "roofline64",
                                        "ensemble32", "learned32", "learnedstep32", "train32",
-                                       "weno32"],
+                                       "weno32", "stream"],
                     help="time a single workload/precision (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
-                    help="run only a plain device copy of MIB mebibytes, 20 times (the reference "
-                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+                    help="run only the project's copy kernel on MIB mebibytes, 20 times (the "
+                         "reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the torus step is measured on a single MI355X "
@@ -325,26 +416,24 @@ def main():
     import torch
     from paper_1904_10070_amd import inputs, load_library, WENO5
     load_library()
-
-    class inputs_mod:  # flag values of the C interface used below
-        WENO5_FLAG = WENO5
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     if args.copy_calibration:
+        from paper_1904_10070_amd.binding import hbm_stream, STREAM_COPY
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 20
+        ts = event_reps(lambda: hbm_stream(STREAM_COPY, src, None, dst),
+                        torch.cuda.current_stream(), reps=20)
         print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": 4 * n,
-                          "bytes_written": 4 * n, "gbs_read_plus_write": 8 * n / dt / 1e9}))
+                          "bytes_written": 4 * n,
+                          "gbs_read_plus_write": 8 * n / spread(ts)["median"] / 1e9}))
+        return
+    if args.only == "stream":
+        print(json.dumps(stream_ceiling()))
         return
     if args.only == "ensemble32":
-        print(json.dumps(ensemble_leg(args.steps, args.warmup)))
+        print(json.dumps(ensemble_leg()))
         return
     if args.only == "learnedstep32":
         print(json.dumps(learned_step_timing(args.steps)))
@@ -353,8 +442,8 @@ def main():
         print(json.dumps(training_timing(args.steps)))
         return
     if args.only == "learned32":
-        d = gpu_leg(inputs.spinodal_workload(0.6), 32, args.steps, args.warmup)
-        print(json.dumps(learned_leg(d["t_step"], steps=args.steps)))
+        d = graph_leg(inputs.spinodal_workload(0.6), 32)
+        print(json.dumps(learned_leg(d["t_step"])))
         return
     if args.only:
         wl, prec = args.only[:-2], int(args.only[-2:])
@@ -366,11 +455,13 @@ def main():
                           "value": d["nups"], "unit": "node-updates/s",
                           "ms_per_step": d["t_step"] * 1e3, "achieved_gbs": d["achieved_gbs"],
                           "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
-                          "bytes_per_launch": d["bytes_per_launch"], "steps": args.steps}))
+                          "bytes_per_launch": d["bytes_per_launch"], "steps": args.steps,
+                          "timing": d["timing"]}))
         return
 
     p = inputs.spinodal_workload(0.6)
     head = gpu_leg(p, 32, args.steps, args.warmup)
+    ceiling = stream_ceiling()
     out = {
         "metric": "node-updates/s & % HBM peak, FP32 vs FP64; batched + learned-coarse speedup at err",
         "value": head["nups"],
@@ -387,44 +478,42 @@ def main():
         "config": {"workload": "spinodal coarsening torus 512x1280, r=1, R=2.5, tau=0.6, "
                                "M=2.5e-3, dt=4e-4, FP32 populations",
                    "n_theta": p.n_theta, "n_phi": p.n_phi, "parallelism": "single GPU"},
+        "timing": dict(head["timing"], graph_replayed=args.steps >= GRAPH_CHUNK,
+                       note="REPS repetitions of exactly `steps` steps; value from the median"),
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic("spinodal512x1280_fp32"),
                      "kernel": "tlb_stage_kernel<float>",
                      "bytes_per_launch": head["bytes_per_launch"],
-                     "copy_gbs": copy_bandwidth(),
+                     "copy_gbs": ceiling["copy_gbs"], "stream": ceiling,
+                     "frac_of_stream_mix": head["achieved_gbs"] / ceiling["stage_mix_gbs"],
+                     "copy_gbs_torch": copy_bandwidth(),
                      # the same copy between two buffers of half the three state copies
                      # each (134 MB in all, which stays in the 256 MB last-level cache, as
                      # the working set of this grid does)
-                     "copy_gbs_working_set": copy_bandwidth(
+                     "copy_gbs_working_set_torch": copy_bandwidth(
                          mib=max(1, int(51 * p.n_theta * p.n_phi * 4 / 2 / (1 << 20))), reps=50)},
     }
     if not args.no_extra:
-        steps64 = max(10, args.steps // 2)
-        d = gpu_leg(p, 64, steps64, args.warmup)
-        out["fp64"] = {"value": d["nups"], "unit": "node-updates/s", "ms_per_step": d["t_step"] * 1e3,
-                       "steps": steps64, "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
-                       "achieved_gbs": d["achieved_gbs"]}
+        d = graph_leg(p, 32, seconds=1.0)
+        out["fp32_graph_1s"] = leg_json(d)
+        t_fine = d["t_step"]
+        d = graph_leg(p, 64, seconds=1.0)
+        out["fp64"] = leg_json(d)
         pr = inputs.roofline_workload()
-        steps_r = max(10, args.steps // 20)
-        d = gpu_leg(pr, 32, steps_r, 5)
-        out["fp32_2048x5120"] = {"value": d["nups"], "unit": "node-updates/s",
-                                 "ms_per_step": d["t_step"] * 1e3, "steps": steps_r,
-                                 "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,
-                                 "achieved_gbs": d["achieved_gbs"]}
+        d = graph_leg(pr, 32, seconds=1.0)
+        out["fp32_2048x5120"] = leg_json(
+            d, frac_of_stream_mix=d["achieved_gbs"] / ceiling["stage_mix_gbs"],
+            traffic=measured_traffic("roofline2048x5120_fp32"))
         # the small drop workload (64 x 160, FP64): launch-bound, stepped through the graph
         pd = inputs.drop_workload()
-        d = gpu_leg(pd, 64, 2000, args.warmup, phi=inputs.drop_workload_phi(pd, seed=1))
-        out["drop64x160_fp64"] = {"value": d["nups"], "unit": "node-updates/s",
-                                  "ms_per_step": d["t_step"] * 1e3, "steps": 2000}
+        d = graph_leg(pd, 64, seconds=0.25, phi=inputs.drop_workload_phi(pd, seed=1))
+        out["drop64x160_fp64"] = leg_json(d)
         # the WENO-5 advection variant (nonlinear face weights: arithmetic-bound)
-        d = gpu_leg(p.with_(flags=inputs_mod.WENO5_FLAG), 32, max(10, args.steps // 4), args.warmup)
-        out["weno5_fp32"] = {"value": d["nups"], "unit": "node-updates/s",
-                             "ms_per_step": d["t_step"] * 1e3, "steps": max(10, args.steps // 4),
-                             "vs_uw5": d["nups"] / head["nups"],
-                             "hbm_frac": d["achieved_gbs"] / HBM_PEAK_GBS}
-        out["ensemble64_fp32"] = ensemble_leg(max(10, args.steps // 10), 5)
-        out["learned_coarse_fp32"] = learned_leg(head["t_step"])
+        d = graph_leg(p.with_(flags=WENO5), 32, seconds=0.5)
+        out["weno5_fp32"] = leg_json(d, vs_uw5=d["nups"] / out["fp32_graph_1s"]["value"])
+        out["ensemble64_fp32"] = ensemble_leg()
+        out["learned_coarse_fp32"] = learned_leg(t_fine)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

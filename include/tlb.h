@@ -33,8 +33,11 @@
  * table, a small reduction workspace and the step graph, all freed by tlb_destroy.
  *
  * Streams.  All work is enqueued on the HIP stream given at creation (NULL = the default
- * stream), in call order, asynchronously with respect to the host.  Only tlb_invariants
- * waits for the stream.  A handle must not be used from two host threads at once.
+ * stream), in call order, asynchronously with respect to the host.  The calls that return
+ * host values wait for the stream (tlb_invariants, tlb_structure_length, tlb_autotune,
+ * tlb_diagnostics with a host output, tlb_set_state in precision 32, tlb_step_n with
+ * check_every > 0); the others do not.  A handle must not be used from two host threads at
+ * once.
  *
  * Errors.  Every int32_t-returning function returns TLB_OK (0) or a negative TLB_E* code;
  * tlb_last_error() then returns a message for the calling thread.
@@ -52,17 +55,22 @@ extern "C" {
 #define TLB_EINVAL (-1)     /* bad argument: parameters out of range, NULL where required   */
 #define TLB_ENOMEM (-2)     /* the library's own small allocation failed                    */
 #define TLB_EHIP (-3)       /* a HIP runtime call or kernel launch failed                    */
-#define TLB_ENONFINITE (-4) /* tlb_invariants found NaN or Inf in the state                  */
+#define TLB_ENONFINITE (-4) /* NaN or Inf in the state (tlb_invariants, or a check of        *
+                             * tlb_step_n under check_every)                               */
+#define TLB_EUNSTABLE (-5)  /* dt exceeds the explicit stability bound of tlb_stable_dt     *
+                             * (reported only for grids created with TLB_STRICT_DT)         */
 
 /* flags */
 #define TLB_FLAT 1u            /* flat limit: J = R and G = 0 (a doubly periodic plane with   *
                                 * spacings R dphi and r dtheta)                              */
 #define TLB_CH_NO_ADVECTION 2u /* drop -div(u phi) from the Cahn-Hilliard equation          */
 #define TLB_NO_GRAPH 4u        /* tlb_step_n launches every kernel itself instead of replaying *
-                                * a prebuilt graph of 32 time steps (same results, bit-exact) */
+                                * prebuilt graphs of the step loop (same results, bit-exact)  */
 #define TLB_WENO5 8u           /* advection face values by the nonlinear WENO-5 reconstruction *
                                 * (Jiang-Shu weights, eps = 1e-6) instead of the linear UW5   *
                                 * one; tiles of 8 rows only, not in batches                   */
+#define TLB_STRICT_DT 16u      /* tlb_create_torus_grid refuses (TLB_EUNSTABLE) a dt above the *
+                                * bound of tlb_stable_dt                                       */
 
 /* Physical and numerical parameters, in the paper's units (k_B T = m = 1, so the kinematic
  * viscosity is nu = tau, eq. nu).
@@ -73,18 +81,27 @@ extern "C" {
  *   tau         BGK relaxation time (> 0)
  *   dt          time step of the three-stage SSP Runge-Kutta integrator (> 0)
  *   precision   32 or 64: element type T of every device buffer of this grid
- *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH                               */
+ *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT
+ *   check_every 0: tlb_step_n does not look at the state.  K > 0: tlb_step_n counts the
+ *               non-finite values of the state (f and phi) after every K steps of a call and
+ *               after its last step, waits for the stream at its end and returns
+ *               TLB_ENONFINITE if any count was non-zero (the steps after a failed check still
+ *               run; nothing is rolled back).  Each check reads the state once, about 1/8 of
+ *               the memory traffic of a step.                                               */
 typedef struct tlb_params {
   double r, R;
   int32_t n_theta, n_phi;
   double A, kappa, M, tau, dt;
   int32_t precision;
   uint32_t flags;
+  int32_t check_every;
 } tlb_params;
 
 /* The three state copies the integrator cycles through (device pointers, each of the
  * layout above).  Copy 0 holds the current state between calls; copies 1 and 2 hold
- * Runge-Kutta stage values and are scratch to the caller.  All six must be distinct.   */
+ * Runge-Kutta stage values and are scratch to the caller.  All six must be distinct.
+ * Rows are dense (the row pitch is n_phi elements): the halo copies of the stage kernel
+ * handle rows of any length, so no padding is asked for.                                  */
 typedef struct tlb_buffers {
   void* f[3];
   void* phi[3];
@@ -92,12 +109,28 @@ typedef struct tlb_buffers {
 
 typedef struct tlb_grid tlb_grid;
 
+/* Explicit stability bound of the time step for these parameters (host only, no GPU work):
+ * the smallest of
+ *   upwind advection at Courant number 1 along both angles over the smallest spacings,
+ *     1 / (v_max (1/h_theta + 1/h_phi)),  v_max = sqrt(3 + sqrt 6) (eq. vmatrix),
+ *     h_theta = r dtheta, h_phi = (R - r) dphi (the inner equator; R dphi if TLB_FLAT);
+ *   BGK relaxation, 2.5 tau (the real-axis limit 2.51 of SSP-RK3 for the decay rate 1/tau);
+ *   Cahn-Hilliard, 2.51 / (M kappa S^2 + 2 M |A| S), S = 4/h_theta^2 + 4/h_phi^2 the largest
+ *     eigenvalue of the five-point surface Laplacian (eq. CH with eq. mu linearised about
+ *     phi = 0).
+ * The paper lowers its time step tenfold for the thick torus because of the small spacing at
+ * its inner equator (section IV); the bound falls with that spacing in the same way.  Only
+ * r, R, n_theta, n_phi, A, kappa, M, tau and flags are read.  Errors: TLB_EINVAL (the
+ * parameters as for creation, dt aside).                                                   */
+int32_t tlb_stable_dt(const tlb_params* params, double* dt_max);
+
 /* Validate the parameters, build the per-row geometry of the torus (appendix A: metric
  * factors r and J = R + r cos theta at the nodes and half-nodes, connection coefficient
  * G = Gamma_{theta phi phi} = sin theta / J, eq. conn_torus) and the velocity-space
  * constants (eq. vmatrix, the weights w_k and the derivative kernel K^H of section II C),
  * and return a handle.  Errors: TLB_EINVAL (r <= 0, R <= r, a grid side < 1, dt, tau <= 0,
- * kappa or M < 0, precision not 32/64, any NULL pointer or buffer), TLB_ENOMEM, TLB_EHIP. */
+ * kappa or M < 0, precision not 32/64, check_every < 0, any NULL pointer or buffer),
+ * TLB_EUNSTABLE (TLB_STRICT_DT set and dt > tlb_stable_dt), TLB_ENOMEM, TLB_EHIP.         */
 int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffers,
                               void* hip_stream, tlb_grid** out);
 
@@ -116,10 +149,12 @@ int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void
  * f_eq (eq. feq); finite-difference advection along the vielbein frame with the metric
  * factors r and J (eq. boltz_tor); velocity-space force and connection terms through K^H
  * (section II C); Cahn-Hilliard right-hand side -div(u phi) + M Delta_S mu (eq. CH) --
- * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous.  Runs of 32 steps
- * are replayed from a graph of kernel nodes built on first use (unless TLB_NO_GRAPH); the
- * graph keeps the buffer pointers given at creation.
- * Errors: TLB_EINVAL, TLB_EHIP (launch or graph failure).                                  */
+ * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous (unless check_every
+ * > 0, see tlb_params).  Unless TLB_NO_GRAPH, the steps are replayed from graphs of kernel
+ * nodes: one of 32 steps for every full run of 32 and one of the remainder's length, each
+ * built on first use and kept; the graphs keep the buffer pointers given at creation.
+ * Errors: TLB_EINVAL, TLB_EHIP (launch or graph failure), TLB_ENONFINITE (check_every > 0
+ * and a check of this call found NaN or Inf).                                             */
 int32_t tlb_step_n(tlb_grid* grid, int64_t n_steps);
 
 /* Moments of the current state into caller buffers (any may be NULL): density n = sum f,
@@ -177,10 +212,12 @@ int32_t tlb_autotune(tlb_grid* grid, int32_t* rows);
 /* Ensembles of tori (coarsening statistics over tori of different aspect ratios and grid
  * sizes, section IV): tlb_batch_step_n advances every grid of the batch by n_steps with one
  * persistent fused launch per Runge-Kutta stage covering the tiles of all grids (each grid
- * keeps its own parameters, time step and buffers), replayed from a graph for runs of 32
- * steps.  Each grid ends exactly (bit for bit) where tlb_step_n on it alone would.  The batch
+ * keeps its own parameters, time step and buffers), replayed from graphs as tlb_step_n's.
+ * Each grid ends exactly (bit for bit) where tlb_step_n on it alone would.  The batch
  * keeps pointers to the grids, which must outlive it and must not be stepped on their own
  * between batch calls on different streams.  All grids must have the same precision.
+ * Ensembles whose state copies together exceed 1 GiB use streaming (nontemporal) stage
+ * outputs and y^n loads, as large single grids do; the results are the same.
  * Errors: TLB_EINVAL (NULL, empty, mixed precision, duplicate), TLB_ENOMEM, TLB_EHIP.      */
 typedef struct tlb_batch tlb_batch;
 int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n_grids, void* hip_stream,

@@ -104,7 +104,9 @@ int32_t tlb_cnn_train_step(tlb_cnn* net, const float* moments, const float* targ
 
 /* Sums of x and x^2 of each of the 4 channels of float[count][4] data (device), in FP64
  * with a fixed order: out[c] = sum x_c, out[4 + c] = sum x_c^2 (host array of 8).  For
- * choosing in_shift / in_scale / out_scale.  Waits for the stream.                         */
+ * choosing in_shift / in_scale / out_scale.  Waits for the stream.  The partial sums go to
+ * a 33 KB workspace per device that the first call on the device allocates and the process
+ * keeps (later calls allocate nothing).                                                    */
 int32_t tlb_learn_stats(const float* data, int64_t count, void* hip_stream, double out[8]);
 
 /* Restrict the state of `fine` onto `coarse` (overwriting its state): fine n_theta and n_phi
@@ -122,7 +124,8 @@ int32_t tlb_learn_pair(const tlb_grid* grid, const tlb_grid* truth, float* momen
                        float* targets);
 
 /* Apply corrections float[nt][np][4] (device, physical units) to a grid's state as
- * described above.  Enqueued on the grid's stream.                                         */
+ * described above.  Enqueued on the grid's stream; does not wait and allocates nothing (its
+ * per-row sums use a workspace made with the grid).                                        */
 int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections);
 
 /* n_steps learned coarse steps: each is one tlb_step_n step of the grid followed by the

@@ -5,6 +5,8 @@ The step itself runs in the HIP kernels of libtlb.so (C interface: include/tlb.h
 seeded synthetic initial conditions.
 """
 from . import inputs  # noqa: F401
-from .binding import TorusGrid, TorusBatch, load_library, TlbError, FLAT, CH_NO_ADVECTION, NO_GRAPH, WENO5  # noqa: F401
+from .binding import (TorusGrid, TorusBatch, load_library, stable_dt, TlbError, FLAT,  # noqa: F401
+                      CH_NO_ADVECTION, NO_GRAPH, WENO5, STRICT_DT)
 
-__all__ = ["TorusGrid", "TorusBatch", "load_library", "TlbError", "FLAT", "CH_NO_ADVECTION", "NO_GRAPH", "WENO5", "inputs"]
+__all__ = ["TorusGrid", "TorusBatch", "load_library", "stable_dt", "TlbError", "FLAT",
+           "CH_NO_ADVECTION", "NO_GRAPH", "WENO5", "STRICT_DT", "inputs"]

@@ -17,19 +17,22 @@ TLB_EINVAL = -1
 TLB_ENOMEM = -2
 TLB_EHIP = -3
 TLB_ENONFINITE = -4
+TLB_EUNSTABLE = -5
 
 FLAT = 1
 CH_NO_ADVECTION = 2
 NO_GRAPH = 4
 WENO5 = 8
+STRICT_DT = 16
 
-EXPORTED = ("tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
+EXPORTED = ("tlb_stable_dt", "tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",
             "tlb_last_error", "tlb_set_tile_rows", "tlb_autotune", "tlb_create_batch",
             "tlb_batch_step_n", "tlb_batch_autotune", "tlb_destroy_batch", "tlb_structure_length",
             "tlb_cnn_create", "tlb_cnn_destroy", "tlb_cnn_set_params", "tlb_cnn_get_params",
             "tlb_cnn_forward", "tlb_cnn_gradient", "tlb_cnn_train_step", "tlb_learn_stats",
-            "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n")
+            "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n",
+            "tlb_hbm_stream")
 
 CNN_PARAMS = 30660
 
@@ -45,7 +48,8 @@ class Params(ctypes.Structure):
                 ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
                 ("A", ctypes.c_double), ("kappa", ctypes.c_double), ("M", ctypes.c_double),
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("check_every", ctypes.c_int32)]
 
 
 class Buffers(ctypes.Structure):
@@ -80,6 +84,8 @@ def load_library(path=None):
         raise RuntimeError(f"{path} not found: build it first (python -m paper_1904_10070_amd.build)")
     lib = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.tlb_stable_dt.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double)]
+    lib.tlb_stable_dt.restype = i32
     lib.tlb_create_torus_grid.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Buffers), vp,
                                           ctypes.POINTER(vp)]
     lib.tlb_create_torus_grid.restype = i32
@@ -127,6 +133,8 @@ def load_library(path=None):
     lib.tlb_learn_pair.argtypes = [vp, vp, vp, vp]
     lib.tlb_apply_correction.argtypes = [vp, vp]
     lib.tlb_learned_step_n.argtypes = [vp, vp, i64]
+    lib.tlb_hbm_stream.argtypes = [i32, vp, vp, vp, i64, vp]
+    lib.tlb_hbm_stream.restype = i32
     for name in ("tlb_cnn_create", "tlb_cnn_set_params", "tlb_cnn_get_params",
                  "tlb_cnn_forward", "tlb_cnn_gradient", "tlb_cnn_train_step", "tlb_learn_stats",
                  "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n"):
@@ -144,14 +152,28 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def stable_dt(params, precision=64):
+    """Explicit stability bound of the time step (tlb_stable_dt; host only, no GPU needed)."""
+    lib = load_library()
+    p = Params(params.r, params.R, int(params.n_theta), int(params.n_phi), params.A, params.kappa,
+               params.M, params.tau, params.dt, precision, int(getattr(params, "flags", 0)), 0)
+    out = ctypes.c_double()
+    _check(lib, lib.tlb_stable_dt(ctypes.byref(p), ctypes.byref(out)), "tlb_stable_dt")
+    return out.value
+
+
 class TorusGrid:
     """A torus grid whose state lives in torch-owned device memory and is stepped by libtlb.
 
     params: an object with the fields of tlb_params (e.g. inputs.TorusParams).
     precision: 32 or 64.  stream: a torch.cuda.Stream (default: the current stream).
+    check_every: tlb_params.check_every (0: no non-finite checks in step()).
+    buffers: optional (f, phi), two lists of three torch tensors to use as the state copies
+    instead of new ones (e.g. those of a grid closed before).
     """
 
-    def __init__(self, params, precision=64, device="cuda", stream=None):
+    def __init__(self, params, precision=64, device="cuda", stream=None, check_every=0,
+                 buffers=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -165,10 +187,19 @@ class TorusGrid:
         self.shape = (nt, np_)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         # state copies: 0 = current state, 1 and 2 = Runge-Kutta stage scratch
-        self.f = [torch.zeros((16, nt, np_), dtype=self.dtype, device=self.device) for _ in range(3)]
-        self.phi = [torch.zeros((nt, np_), dtype=self.dtype, device=self.device) for _ in range(3)]
+        if buffers is not None:
+            self.f, self.phi = list(buffers[0]), list(buffers[1])
+            for t in self.f + self.phi:
+                assert t.dtype == self.dtype and t.is_contiguous() and t.is_cuda
+            assert all(tuple(t.shape) == (16, nt, np_) for t in self.f)
+            assert all(tuple(t.shape) == (nt, np_) for t in self.phi)
+        else:
+            self.f = [torch.zeros((16, nt, np_), dtype=self.dtype, device=self.device)
+                      for _ in range(3)]
+            self.phi = [torch.zeros((nt, np_), dtype=self.dtype, device=self.device)
+                        for _ in range(3)]
         p = Params(params.r, params.R, nt, np_, params.A, params.kappa, params.M, params.tau,
-                   params.dt, precision, int(getattr(params, "flags", 0)))
+                   params.dt, precision, int(getattr(params, "flags", 0)), int(check_every))
         b = Buffers()
         for i in range(3):
             b.f[i] = self.f[i].data_ptr()
@@ -449,3 +480,19 @@ def apply_correction(grid, corrections):
 
 def learned_step(grid, net, nsteps):
     _check(grid.lib, grid.lib.tlb_learned_step_n(grid._h, net._h, int(nsteps)), "tlb_learned_step_n")
+
+
+STREAM_COPY, STREAM_ADD, STREAM_READ = 0, 1, 2
+
+
+def hbm_stream(mode, x, y, z, stream=None):
+    """tlb_hbm_stream on torch device tensors (16-byte aligned, contiguous): mode 0 copies x to
+    z, mode 1 writes x + y (as floats) to z, mode 2 reads x (z receives one 16-byte partial per
+    workgroup).  Enqueued on `stream` (default: the current stream); returns the bytes moved."""
+    import torch
+    lib = load_library()
+    n16 = x.numel() * x.element_size() // 16
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib, lib.tlb_hbm_stream(int(mode), _ptr(x), _ptr(y), _ptr(z), int(n16),
+                                   ctypes.c_void_p(s.cuda_stream)), "tlb_hbm_stream")
+    return 16 * n16 * (2 if mode == STREAM_COPY else 3 if mode == STREAM_ADD else 1)

@@ -5,7 +5,8 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", "tlb.hip"), os.path.join(PKG, "csrc", "learn.hip")]
+SRCS = [os.path.join(PKG, "csrc", "tlb.hip"), os.path.join(PKG, "csrc", "learn.hip"),
+        os.path.join(PKG, "csrc", "stream.hip")]
 LIB = os.path.join(PKG, "libtlb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -793,6 +794,30 @@ int32_t run_all(const std::vector<tlbi_launch>& seq, hipStream_t stream) {
 
 int blocks_for(long long n, int threads) { return (int)((n + threads - 1) / threads); }
 
+// Partials of tlb_learn_stats: STATS_BLOCKS x 8 doubles plus the 8 results, one buffer per
+// device, made on the first call on that device and kept until the process ends (calls on
+// one device are stream-ordered through it; tlb_learn_stats waits for its stream).
+constexpr int STATS_BLOCKS = 512;
+constexpr int MAX_DEVICES = 64;
+
+int32_t stats_workspace(double** out) {
+  static std::mutex mu;
+  static double* ws[MAX_DEVICES] = {};
+  int dev = 0;
+  LRN_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return tlbi_fail(TLB_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ws[dev]) {
+    const hipError_t e = hipMalloc(&ws[dev], (STATS_BLOCKS * 8 + 8) * sizeof(double));
+    if (e != hipSuccess) {
+      ws[dev] = nullptr;
+      return tlbi_fail(TLB_ENOMEM, std::string("stats workspace: ") + hipGetErrorString(e));
+    }
+  }
+  *out = ws[dev];
+  return TLB_OK;
+}
+
 }  // namespace
 
 struct tlb_cnn {
@@ -820,7 +845,7 @@ struct tlb_cnn {
   int red_blocks;
   // graph of LEARN_GRAPH_CHUNK learned steps, bound to one grid's buffers and tile shape
   hipGraphExec_t chunk_exec;
-  const tlb_grid* chunk_grid;
+  unsigned long long chunk_grid;  // uid of the grid the graph was built for (0: none)
   void* chunk_key[7];
   unsigned chunk_version;  // the grid's version when the graph was built
 };
@@ -1047,7 +1072,7 @@ void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) 
 void drop_learn_graph(tlb_cnn* net) {
   if (net->chunk_exec) (void)hipGraphExecDestroy(net->chunk_exec);
   net->chunk_exec = nullptr;
-  net->chunk_grid = nullptr;
+  net->chunk_grid = 0;
 }
 
 int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
@@ -1080,7 +1105,7 @@ int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
     net->chunk_exec = nullptr;
     return tlbi_fail(TLB_EHIP, std::string("learned-step graph: ") + hipGetErrorString(e));
   }
-  net->chunk_grid = g;
+  net->chunk_grid = g->uid;
   net->chunk_version = g->version;
   void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
                   reinterpret_cast<void*>((intptr_t)g->ty)};
@@ -1088,8 +1113,12 @@ int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
   return TLB_OK;
 }
 
+// The graph keeps the stage arguments (time step, parameters, per-row tables) of the grid it
+// was built for; a grid is identified by its process-unique id, not its address, since a new
+// grid may be created at a destroyed one's address with the same state buffers.
 bool graph_matches(const tlb_cnn* net, const tlb_grid* g) {
-  if (!net->chunk_exec || net->chunk_grid != g || net->chunk_version != g->version) return false;
+  if (!net->chunk_exec || net->chunk_grid != g->uid || net->chunk_version != g->version)
+    return false;
   void* key[7] = {g->f[0], g->f[1], g->f[2], g->phi[0], g->phi[1], g->phi[2],
                   reinterpret_cast<void*>((intptr_t)g->ty)};
   return std::memcmp(net->chunk_key, key, sizeof(key)) == 0;
@@ -1300,19 +1329,20 @@ int32_t tlb_cnn_train_step(tlb_cnn* net, const float* moments, const float* targ
 int32_t tlb_learn_stats(const float* data, int64_t count, void* hip_stream, double out[8]) {
   if (!data || !out || count < 1) return tlbi_fail(TLB_EINVAL, "data, out or count invalid");
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  const int blocks = 512;
+  const int blocks = STATS_BLOCKS;
   double* part = nullptr;
-  LRN_HIP_CHECK(hipMalloc(&part, (blocks * 8 + 8) * sizeof(double)));
+  int32_t wrc = stats_workspace(&part);
+  if (wrc != TLB_OK) return wrc;
   StatArgs a{data, count, part};
   std::vector<tlbi_launch> seq;
   seq.push_back(make_launch(reinterpret_cast<const void*>(&stats_kernel), dim3(blocks), dim3(RED), a));
   SumArgs s{part, part + blocks * 8, blocks, 8, 1.0};
   seq.push_back(make_launch(reinterpret_cast<const void*>(&sum_partials_kernel), dim3(1), dim3(RED), s));
   int32_t rc = run_all(seq, stream);
-  hipError_t e = hipStreamSynchronize(stream);
-  if (rc == TLB_OK && e == hipSuccess)
-    e = hipMemcpy(out, part + blocks * 8, 8 * sizeof(double), hipMemcpyDeviceToHost);
-  (void)hipFree(part);
+  hipError_t e = hipSuccess;
+  if (rc == TLB_OK)
+    e = hipMemcpyAsync(out, part + blocks * 8, 8 * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (rc == TLB_OK && e == hipSuccess) e = hipStreamSynchronize(stream);
   if (rc != TLB_OK) return rc;
   if (e != hipSuccess) return tlbi_fail(TLB_EHIP, std::string("stats: ") + hipGetErrorString(e));
   return TLB_OK;
@@ -1384,20 +1414,15 @@ int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections) {
   int32_t rc = check_grid(grid, "grid");
   if (rc != TLB_OK) return rc;
   if (!corrections) return tlbi_fail(TLB_EINVAL, "corrections is NULL");
-  double* proj = nullptr;
-  LRN_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&proj), grid->p.n_theta * 3 * sizeof(double)));
+  // the per-row sums go to the grid's own workspace (made with the grid): stream-ordered, so
+  // successive corrections on one grid reuse it in order
   const float one[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   std::vector<tlbi_launch> seq;
   if (grid->p.precision == 64)
-    apply_launches<double>(grid, corrections, one, proj, 0, seq);
+    apply_launches<double>(grid, corrections, one, grid->proj, 0, seq);
   else
-    apply_launches<float>(grid, corrections, one, proj, 0, seq);
-  rc = run_all(seq, grid->stream);
-  const hipError_t e = hipStreamSynchronize(grid->stream);
-  (void)hipFree(proj);
-  if (rc == TLB_OK && e != hipSuccess)
-    rc = tlbi_fail(TLB_EHIP, std::string("apply: ") + hipGetErrorString(e));
-  return rc;
+    apply_launches<float>(grid, corrections, one, grid->proj, 0, seq);
+  return run_all(seq, grid->stream);
 }
 
 int32_t tlb_learned_step_n(tlb_grid* grid, tlb_cnn* net, int64_t n_steps) {

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a)
 // the stage arguments of grid g; tile_begin[g] is the first tile of grid g in the concatenated
 // tile order (tile_begin[n] = total).  XCD x owns a contiguous range of that order, which its
 // gridDim.x / 8 resident blocks walk with a stride, tile by tile.
-template <typename T, bool VEC, int TY, bool GENREF = false>
+template <typename T, bool VEC, int TY, bool GENREF = false, bool STREAM = false>
 __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
     const StageArgs<T>* __restrict__ table, const int* __restrict__ tile_begin, int n, int stage) {
   const int total = tile_begin[n];
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
     const StageArgs<T> a = table[3 * lo + stage - 1];
     int tx, ty;
     band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
-    stage_tile<T, VEC, TY, false, false, GENREF>(a, tx, ty);
+    stage_tile<T, VEC, TY, false, STREAM, GENREF>(a, tx, ty);
     __syncthreads();  // the next tile reuses the LDS tiles
   }
 }
@@ -753,6 +754,25 @@ __global__ __launch_bounds__(256) void tlb_offset_kernel(T* f, long long plane, 
     f[k * plane + x] += scale * T(rest_offset<T>(k));
   });
 }
+
+// Non-finite check of a state (tlb_step_n with check_every > 0): sets *flag to 1 if any
+// population or phi value is NaN or Inf.  Grid-stride loop, one vector store per wave that saw
+// one (several waves may store the same value).
+template <typename T>
+__global__ __launch_bounds__(256) void tlb_nonfinite_kernel(const T* f, const T* phi,
+                                                           long long plane, int* flag) {
+  bool bad = false;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < plane;
+       x += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) bad = bad || !isfinite(f[k * plane + x]);
+    bad = bad || !isfinite(phi[x]);
+  }
+  if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+// *flag = value (a kernel, not a memset: the step loop may be captured into a graph)
+__global__ void tlb_set_flag_kernel(int* flag, int value) { *flag = value; }
 
 // moments and chemical potential of a state, one thread per node
 template <typename T>
@@ -1059,6 +1079,8 @@ void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
+constexpr int GRAPH_CHUNK_B = TLBI_GRAPH_CHUNK;
+
 struct tlb_batch {
   tlb_grid** grids;
   int n;
@@ -1068,8 +1090,8 @@ struct tlb_batch {
   void* table;      // StageArgs<T>[3 n] (device)
   int* tile_begin;  // [n + 1] (device)
   int total_tiles;
-  hipGraphExec_t chunk_exec;
-  bool chunk_tried;
+  hipGraphExec_t graphs[GRAPH_CHUNK_B + 1];  // as tlb_grid::graphs, for the whole batch
+  bool streaming;      // the ensemble's state copies exceed STREAMING_BYTES
   unsigned* versions;  // [n]: the grids' versions when the table was built
 };
 
@@ -1154,7 +1176,16 @@ const void* stage_fn(const tlb_grid* g) {
 }
 
 template <typename T, bool VEC, bool GENREF>
-const void* batch_fn_ty(int ty) {
+const void* batch_fn_ty(int ty, bool streaming) {
+  if (streaming) {  // as for single grids, the 16-byte-copy form only
+    if constexpr (VEC) {
+      switch (ty) {
+        case 4: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, true, 4, GENREF, true>);
+        case 16: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, true, 16, GENREF, true>);
+        default: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, true, 8, GENREF, true>);
+      }
+    }
+  }
   switch (ty) {
     case 4: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 4, GENREF>);
     case 16: return reinterpret_cast<const void*>(&tlb_stage_batch_kernel<T, VEC, 16, GENREF>);
@@ -1162,13 +1193,17 @@ const void* batch_fn_ty(int ty) {
   }
 }
 
-// the batch kernel for the batch's current grids (the general-reference form if any needs it)
+// the batch kernel for the batch's current grids (the general-reference form if any needs it;
+// streaming accesses when the ensemble's state copies together exceed STREAMING_BYTES)
 template <typename T>
 const void* batch_fn(const tlb_batch* b) {
   bool gen = false;
   for (int i = 0; i < b->n; ++i) gen = gen || general_reference<T>(b->grids[i]);
-  if (gen) return b->vec ? batch_fn_ty<T, true, true>(b->ty) : batch_fn_ty<T, false, true>(b->ty);
-  return b->vec ? batch_fn_ty<T, true, false>(b->ty) : batch_fn_ty<T, false, false>(b->ty);
+  if (gen)
+    return b->vec ? batch_fn_ty<T, true, true>(b->ty, b->streaming)
+                  : batch_fn_ty<T, false, true>(b->ty, b->streaming);
+  return b->vec ? batch_fn_ty<T, true, false>(b->ty, b->streaming)
+                : batch_fn_ty<T, false, false>(b->ty, b->streaming);
 }
 
 int stage_blocks(const tlb_grid* g) {
@@ -1184,21 +1219,23 @@ int32_t launch_stage(tlb_grid* g, int stage) {
   return TLB_OK;
 }
 
-// A chain of GRAPH_CHUNK time steps (3 GRAPH_CHUNK kernel nodes, each depending on the one
-// before) built explicitly -- no stream capture, so the caller's stream may be the legacy
-// default stream -- and replayed with one launch.  Kernel nodes only.
-constexpr int GRAPH_CHUNK = 32;
+// A chain of `steps` time steps (3 `steps` kernel nodes, each depending on the one before)
+// built explicitly -- no stream capture, so the caller's stream may be the legacy default
+// stream -- and replayed with one launch.  Kernel nodes only.  Runs of GRAPH_CHUNK steps
+// replay the longest chain; a shorter run, or the remainder of a longer one, replays a chain of
+// its own length (built on first use and kept), so every step of the loop is a graph replay.
+constexpr int GRAPH_CHUNK = TLBI_GRAPH_CHUNK;
 
 // `make_params(st)` returns the kernel-argument array of stage st (1..3); the arrays must stay
 // valid until the graph is instantiated
 template <class MakeParams>
 hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_params,
-                       hipGraphExec_t* out) {
+                       int steps, hipGraphExec_t* out) {
   hipGraph_t graph;
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return e;
   hipGraphNode_t prev = nullptr;
-  for (int t = 0; t < GRAPH_CHUNK && e == hipSuccess; ++t)
+  for (int t = 0; t < steps && e == hipSuccess; ++t)
     for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
       hipKernelNodeParams kp{};
       kp.func = const_cast<void*>(fn);
@@ -1218,41 +1255,56 @@ hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_pa
 }
 
 template <typename T>
-int32_t build_chunk_graph(tlb_grid* g) {
+int32_t build_step_graph(tlb_grid* g, int steps) {
   StageArgs<T> args[3] = {stage_args<T>(g, 1), stage_args<T>(g, 2), stage_args<T>(g, 3)};
   void* params[3][1] = {{&args[0]}, {&args[1]}, {&args[2]}};
   hipError_t e = build_chain(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(TX * g->ty),
-                             [&](int st) { return params[st - 1]; }, &g->chunk_exec);
+                             [&](int st) { return params[st - 1]; }, steps, &g->graphs[steps]);
   if (e != hipSuccess) return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
   return TLB_OK;
 }
 
 void drop_graph(tlb_grid* g) {
-  if (g->chunk_exec) (void)hipGraphExecDestroy(g->chunk_exec);
-  g->chunk_exec = nullptr;
-  g->chunk_tried = false;
+  for (hipGraphExec_t& x : g->graphs) {
+    if (x) (void)hipGraphExecDestroy(x);
+    x = nullptr;
+  }
+}
+
+template <typename T>
+int32_t check_t(tlb_grid* g) {
+  const long long plane = (long long)g->p.n_theta * g->p.n_phi;
+  const int blocks = (int)std::min<long long>(4096, (plane + 255) / 256);
+  hipLaunchKernelGGL(tlb_nonfinite_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
+                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]), plane,
+                     g->check_flag);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
 }
 
 template <typename T>
 int32_t step_n_t(tlb_grid* g, int64_t n) {
-  const bool use_graph = !(g->p.flags & TLB_NO_GRAPH) && n >= GRAPH_CHUNK;
-  if (g->chunk_tried && g->chunk_version != g->version) drop_graph(g);  // stale arguments
-  if (use_graph && !g->chunk_tried) {
-    g->chunk_tried = true;
-    g->chunk_version = g->version;
-    int32_t rc = build_chunk_graph<T>(g);
-    if (rc != TLB_OK) return rc;
+  if (g->graph_version != g->version) {  // stage arguments changed: the graphs are stale
+    drop_graph(g);
+    g->graph_version = g->version;
   }
-  int64_t done = 0;
-  if (use_graph && g->chunk_exec) {
-    for (; done + GRAPH_CHUNK <= n; done += GRAPH_CHUNK)
-      TLB_HIP_CHECK(hipGraphLaunch(g->chunk_exec, g->stream));
+  if (g->p.flags & TLB_NO_GRAPH) {
+    for (int64_t done = 0; done < n; ++done)
+      for (int st = 1; st <= 3; ++st) {
+        int32_t rc = launch_stage<T>(g, st);
+        if (rc != TLB_OK) return rc;
+      }
+    return TLB_OK;
   }
-  for (; done < n; ++done)
-    for (int st = 1; st <= 3; ++st) {
-      int32_t rc = launch_stage<T>(g, st);
+  for (int64_t done = 0; done < n;) {
+    const int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);
+    if (!g->graphs[s]) {
+      int32_t rc = build_step_graph<T>(g, s);
       if (rc != TLB_OK) return rc;
     }
+    TLB_HIP_CHECK(hipGraphLaunch(g->graphs[s], g->stream));
+    done += s;
+  }
   return TLB_OK;
 }
 
@@ -1325,9 +1377,10 @@ int32_t autotune_t(tlb_grid* g, int32_t* chosen) {
 // ---- ensembles ------------------------------------------------------------------------------
 
 void drop_batch_graph(tlb_batch* b) {
-  if (b->chunk_exec) (void)hipGraphExecDestroy(b->chunk_exec);
-  b->chunk_exec = nullptr;
-  b->chunk_tried = false;
+  for (hipGraphExec_t& x : b->graphs) {
+    if (x) (void)hipGraphExecDestroy(x);
+    x = nullptr;
+  }
 }
 
 // (Re)build the argument table and the tile offsets of the batch for its tile height, and the
@@ -1388,30 +1441,25 @@ int32_t batch_launch_t(tlb_batch* b, int stage) {
 
 template <typename T>
 int32_t batch_step_t(tlb_batch* b, int64_t n) {
-  if (n >= GRAPH_CHUNK && !b->chunk_tried) {
-    b->chunk_tried = true;
-    const void* fn = batch_fn<T>(b);
-    const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
-    const int* tile_begin = b->tile_begin;
-    int nn = b->n;
-    int stages[3] = {1, 2, 3};
-    void* params[3][4] = {{&table, &tile_begin, &nn, &stages[0]},
-                          {&table, &tile_begin, &nn, &stages[1]},
-                          {&table, &tile_begin, &nn, &stages[2]}};
-    hipError_t e = build_chain(fn, dim3(b->blocks), dim3(TX * b->ty),
-                               [&](int st) { return params[st - 1]; }, &b->chunk_exec);
-    if (e != hipSuccess)
-      return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
-  }
-  int64_t done = 0;
-  if (n >= GRAPH_CHUNK && b->chunk_exec)
-    for (; done + GRAPH_CHUNK <= n; done += GRAPH_CHUNK)
-      TLB_HIP_CHECK(hipGraphLaunch(b->chunk_exec, b->stream));
-  for (; done < n; ++done)
-    for (int st = 1; st <= 3; ++st) {
-      int32_t rc = batch_launch_t<T>(b, st);
-      if (rc != TLB_OK) return rc;
+  for (int64_t done = 0; done < n;) {
+    const int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);
+    if (!b->graphs[s]) {
+      const void* fn = batch_fn<T>(b);
+      const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
+      const int* tile_begin = b->tile_begin;
+      int nn = b->n;
+      int stages[3] = {1, 2, 3};
+      void* params[3][4] = {{&table, &tile_begin, &nn, &stages[0]},
+                            {&table, &tile_begin, &nn, &stages[1]},
+                            {&table, &tile_begin, &nn, &stages[2]}};
+      hipError_t e = build_chain(fn, dim3(b->blocks), dim3(TX * b->ty),
+                                 [&](int st) { return params[st - 1]; }, s, &b->graphs[s]);
+      if (e != hipSuccess)
+        return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
     }
+    TLB_HIP_CHECK(hipGraphLaunch(b->graphs[s], b->stream));
+    done += s;
+  }
   return TLB_OK;
 }
 
@@ -1551,10 +1599,26 @@ int32_t check_params(const tlb_params* p) {
   if (!std::isfinite(p->A)) return fail(TLB_EINVAL, "A must be finite");
   if (p->precision != 32 && p->precision != 64)
     return fail(TLB_EINVAL, "precision must be 32 or 64");
-  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5))
+  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT))
     return fail(TLB_EINVAL, "unknown flag");
+  if (p->check_every < 0) return fail(TLB_EINVAL, "check_every must be >= 0");
   return TLB_OK;
 }
+
+// The explicit stability bound of tlb_stable_dt (see tlb.h), for validated parameters.
+double stable_dt_bound(const tlb_params& p) {
+  const double v_max = std::sqrt(3.0 + std::sqrt(6.0));
+  const double h_t = p.r * 2.0 * M_PI / p.n_theta;
+  const double h_p = ((p.flags & TLB_FLAT) ? p.R : p.R - p.r) * 2.0 * M_PI / p.n_phi;
+  const double dt_adv = 1.0 / (v_max * (1.0 / h_t + 1.0 / h_p));
+  const double dt_bgk = 2.5 * p.tau;
+  const double S = 4.0 / (h_t * h_t) + 4.0 / (h_p * h_p);
+  const double ch = p.M * p.kappa * S * S + 2.0 * p.M * std::fabs(p.A) * S;
+  const double dt_ch = ch > 0.0 ? 2.51 / ch : INFINITY;
+  return std::min(dt_adv, std::min(dt_bgk, dt_ch));
+}
+
+std::atomic<unsigned long long> g_next_uid{1};
 
 }  // namespace
 
@@ -1651,6 +1715,10 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   *out = nullptr;
   int32_t rc = check_params(params);
   if (rc != TLB_OK) return rc;
+  if ((params->flags & TLB_STRICT_DT) && params->dt > stable_dt_bound(*params))
+    return fail(TLB_EUNSTABLE, "dt " + std::to_string(params->dt) +
+                                   " exceeds the stability bound " +
+                                   std::to_string(stable_dt_bound(*params)));
   if (!buffers) return fail(TLB_EINVAL, "buffers is NULL");
   for (int i = 0; i < 3; ++i)
     if (!buffers->f[i] || !buffers->phi[i]) return fail(TLB_EINVAL, "a state buffer is NULL");
@@ -1671,6 +1739,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   g->elem = params->precision == 64 ? sizeof(double) : sizeof(float);
   g->ty = DEFAULT_TY;
   g->n_ref = 1.0;
+  g->uid = g_next_uid.fetch_add(1);
   const int nt = params->n_theta;
   g->rows_per_block = nt <= 512 ? 1 : (nt + 511) / 512;
   g->red_blocks = (nt + g->rows_per_block - 1) / g->rows_per_block;
@@ -1687,6 +1756,8 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
     if (g->area) (void)hipFree(g->area);
     if (g->partial) (void)hipFree(g->partial);
     if (g->half_len) (void)hipFree(g->half_len);
+    if (g->check_flag) (void)hipFree(g->check_flag);
+    if (g->proj) (void)hipFree(g->proj);
     delete g;
     return fail(code, msg);
   };
@@ -1702,6 +1773,8 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
     e = hipMalloc(reinterpret_cast<void**>(&g->partial),
                   sizeof(double) * (3 * g->red_blocks + 3));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->half_len), sizeof(double) * nt);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->check_flag), sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->proj), sizeof(double) * 3 * nt);
   if (e != hipSuccess)
     return cleanup(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipMemcpyAsync(g->rows, host_rows, row_bytes * nt, hipMemcpyHostToDevice, g->stream);
@@ -1728,6 +1801,8 @@ void tlb_destroy(tlb_grid* g) {
   (void)hipFree(g->area);
   (void)hipFree(g->partial);
   (void)hipFree(g->half_len);
+  (void)hipFree(g->check_flag);
+  (void)hipFree(g->proj);
   delete g;
 }
 
@@ -1761,11 +1836,43 @@ int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n
   return init_feq_t<float>(g, n, ut, up);
 }
 
+int32_t tlb_stable_dt(const tlb_params* params, double* dt_max) {
+  g_last_error.clear();
+  if (!dt_max) return fail(TLB_EINVAL, "dt_max is NULL");
+  if (!params) return fail(TLB_EINVAL, "params is NULL");
+  tlb_params p = *params;
+  p.dt = 1.0;  // the bound does not depend on dt; let validation look at the rest
+  int32_t rc = check_params(&p);
+  if (rc != TLB_OK) return rc;
+  *dt_max = stable_dt_bound(p);
+  return TLB_OK;
+}
+
 int32_t tlb_step_n(tlb_grid* g, int64_t n_steps) {
   g_last_error.clear();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
-  return g->p.precision == 64 ? step_n_t<double>(g, n_steps) : step_n_t<float>(g, n_steps);
+  const bool dbl = g->p.precision == 64;
+  const int64_t every = g->p.check_every;
+  if (every <= 0) return dbl ? step_n_t<double>(g, n_steps) : step_n_t<float>(g, n_steps);
+  // checked run: clear the flag, step in runs of check_every with a check after each run (and
+  // after the last step), then wait and report
+  hipLaunchKernelGGL(tlb_set_flag_kernel, dim3(1), dim3(1), 0, g->stream, g->check_flag, 0);
+  TLB_HIP_CHECK(hipGetLastError());
+  int64_t done = 0;
+  do {
+    const int64_t m = std::min(every, n_steps - done);
+    int32_t rc = dbl ? step_n_t<double>(g, m) : step_n_t<float>(g, m);
+    if (rc == TLB_OK) rc = dbl ? check_t<double>(g) : check_t<float>(g);
+    if (rc != TLB_OK) return rc;
+    done += m;
+  } while (done < n_steps);
+  int flag = 0;
+  TLB_HIP_CHECK(hipMemcpyAsync(&flag, g->check_flag, sizeof(int), hipMemcpyDeviceToHost,
+                               g->stream));
+  TLB_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (flag) return fail(TLB_ENONFINITE, "non-finite values in the state after a checked run");
+  return TLB_OK;
 }
 
 int32_t tlb_get_moments(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu) {
@@ -1860,11 +1967,14 @@ int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tl
   b->ty = DEFAULT_TY;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->vec = true;
+  double state_bytes = 0.0;
   for (int i = 0; i < n; ++i) {
     b->grids[i] = grids[i];
     b->vec = b->vec && (b->precision == 64 ? vec_ok<double>(grids[i]->p.n_phi)
                                            : vec_ok<float>(grids[i]->p.n_phi));
+    state_bytes += 51.0 * grids[i]->p.n_theta * (double)grids[i]->p.n_phi * (double)grids[i]->elem;
   }
+  b->streaming = state_bytes > STREAMING_BYTES;
   const size_t args_bytes = b->precision == 64 ? sizeof(StageArgs<double>) : sizeof(StageArgs<float>);
   hipError_t e = hipMalloc(&b->table, args_bytes * 3 * n);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->tile_begin), sizeof(int) * (n + 1));

@@ -10,6 +10,10 @@
 
 #include "tlb.h"
 
+// Longest run of time steps replayed as one graph; longer runs replay it repeatedly and a
+// shorter remainder replays a graph of its own length.
+constexpr int TLBI_GRAPH_CHUNK = 32;
+
 // A torus grid: the caller's state buffers, the stream, and the library's per-row tables.
 struct tlb_grid {
   tlb_params p;
@@ -23,12 +27,16 @@ struct tlb_grid {
   int red_blocks, rows_per_block;
   size_t elem;
   int ty;                     // tile height of the stage kernel (4, 8 or 16)
-  hipGraphExec_t chunk_exec;  // GRAPH_CHUNK time steps as one graph (built on first use)
-  bool chunk_tried;
-  unsigned chunk_version;     // version of the grid when chunk_exec was built
+  // graphs[s]: s = 1..TLBI_GRAPH_CHUNK time steps as one graph of kernel nodes, each built on
+  // the first call that needs it; graph_version: the grid's version when they were built
+  hipGraphExec_t graphs[TLBI_GRAPH_CHUNK + 1];
+  unsigned graph_version;
   void* dft_work;  // structure-factor workspace (built on first use): row transforms and twiddles
   double n_ref;      // reference density of FP32 storage (see stores_deviation), a float value
   unsigned version;  // changes whenever n_ref does: stage arguments kept in graphs are stale
+  unsigned long long uid;  // unique over the process: graphs kept elsewhere key on it
+  int* check_flag;   // [1]: set by the non-finite check of tlb_step_n (check_every > 0)
+  double* proj;      // [3 nt]: per-row sums of the learned correction (tlb_apply_correction)
 };
 
 // Records `msg` as the thread's last error and returns `code`.

@@ -35,3 +35,13 @@ def gpu_run(p, phi, n, ut, up, steps, precision=64, f=None):
         g.step(steps)
     f_out, phi_out = g.get_state()
     return g, f_out.double().cpu().numpy(), phi_out.double().cpu().numpy()
+
+
+def velocity_scale(f, n, axis):
+    """max over nodes of sum_k |f_k| |v_k| / n along one velocity axis (0: theta, 1: phi): the
+    size of the terms whose sum is n u, against which the rounding of u is measured."""
+    from oracle import ref
+    v = np.asarray(ref.velocity_set()[0], dtype=np.float64)
+    i, j = np.divmod(np.arange(16), 4)
+    w = np.abs(v[i] if axis == 0 else v[j])
+    return float(((np.abs(f) * w[:, None, None]).sum(axis=0) / n).max())

@@ -41,15 +41,16 @@ def test_every_declared_symbol_is_exported(lib):
 
 def params(**kw):
     d = dict(r=1.0, R=2.5, n_theta=8, n_phi=16, A=0.5, kappa=1e-3, M=0.1, tau=0.5, dt=1e-3,
-             precision=64, flags=0)
+             precision=64, flags=0, check_every=0)
     d.update(kw)
     return binding.Params(**d)
 
 
 @pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=1.0), dict(n_theta=0), dict(n_phi=-3),
                                  dict(dt=0.0), dict(tau=0.0), dict(kappa=-1.0), dict(M=-0.1),
-                                 dict(precision=16), dict(flags=16), dict(A=float("nan")),
-                                 dict(n_theta=100000, n_phi=100000, precision=64)])
+                                 dict(precision=16), dict(flags=32), dict(A=float("nan")),
+                                 dict(n_theta=100000, n_phi=100000, precision=64),
+                                 dict(check_every=-1)])
 def test_create_rejects_bad_parameters(lib, bad):
     p = params(**bad)
     b = binding.Buffers()
@@ -96,7 +97,7 @@ def test_null_handles_rejected(lib):
 
 def test_weno_flag_is_accepted_by_validation(lib):
     """Flag 8 passes parameter validation (the create call then fails only for want of a GPU
-    or succeeds on one); 16 does not."""
+    or succeeds on one); 32 does not."""
     p = params(flags=8)
     b = binding.Buffers()
     for i in range(3):
@@ -159,3 +160,74 @@ def test_learning_entry_points_reject_null(lib):
     assert lib.tlb_apply_correction(None, None) == binding.TLB_EINVAL
     assert lib.tlb_learned_step_n(None, None, 1) == binding.TLB_EINVAL
     lib.tlb_cnn_destroy(None)
+
+
+def bound_by_hand(r, R, nt, np_, A, kappa, M, tau, flat=False):
+    """The stability bound as tlb.h states it, written out here: advection at Courant number 1
+    over the smallest spacings, 2.5 tau, and 2.51 over the Cahn-Hilliard spectral radius."""
+    import math
+    vmax = math.sqrt(3 + math.sqrt(6))
+    ht = r * 2 * math.pi / nt
+    hp = (R if flat else R - r) * 2 * math.pi / np_
+    S = 4 / ht ** 2 + 4 / hp ** 2
+    ch = M * kappa * S * S + 2 * M * abs(A) * S
+    return min(1 / (vmax * (1 / ht + 1 / hp)), 2.5 * tau, 2.51 / ch if ch > 0 else math.inf)
+
+
+@pytest.mark.parametrize("case", [dict(), dict(n_theta=64, n_phi=160, M=0.1, kappa=1.063e-2),
+                                  dict(flags=1, n_theta=32, n_phi=40), dict(tau=1e-4),
+                                  dict(M=0.0, kappa=0.0)])
+def test_stable_dt_is_the_stated_bound(lib, case):
+    p = params(**case)
+    out = ctypes.c_double()
+    assert lib.tlb_stable_dt(ctypes.byref(p), ctypes.byref(out)) == binding.TLB_OK
+    want = bound_by_hand(p.r, p.R, p.n_theta, p.n_phi, p.A, p.kappa, p.M, p.tau,
+                         flat=bool(p.flags & 1))
+    assert abs(out.value - want) <= 1e-15 * want
+
+
+def test_stable_dt_separates_the_papers_thin_and_thick_tori(lib):
+    """Section IV: the coarsening runs on a 400 x 800 torus with R = 2.5, r = 1 use dt = 5e-4;
+    the thick torus R = 2, r = 1.25 (inner-equator spacing 0.00589) needs dt = 5e-5.  The bound
+    admits the first, rejects 5e-4 on the thick torus and admits its 5e-5 (kappa = 5e-4,
+    A = 0.5, M = tau = 2.5e-3)."""
+    import math
+    thin = params(r=1.0, R=2.5, n_theta=400, n_phi=800, A=0.5, kappa=5e-4, M=2.5e-3, tau=2.5e-3)
+    thick = params(r=1.25, R=2.0, n_theta=400, n_phi=800, A=0.5, kappa=5e-4, M=2.5e-3,
+                   tau=2.5e-3)
+    assert abs((2.0 - 1.25) * 2 * math.pi / 800 - 0.00589) < 5e-6
+    b_thin, b_thick = ctypes.c_double(), ctypes.c_double()
+    assert lib.tlb_stable_dt(ctypes.byref(thin), ctypes.byref(b_thin)) == binding.TLB_OK
+    assert lib.tlb_stable_dt(ctypes.byref(thick), ctypes.byref(b_thick)) == binding.TLB_OK
+    assert 5e-4 < b_thin.value
+    assert 5e-5 < b_thick.value < 5e-4
+
+
+def test_strict_dt_reports_unstable_before_any_gpu_work(lib):
+    p = params(n_theta=64, n_phi=160, M=0.1, kappa=1.063e-2, flags=16)
+    bound = ctypes.c_double()
+    assert lib.tlb_stable_dt(ctypes.byref(p), ctypes.byref(bound)) == binding.TLB_OK
+    b = binding.Buffers()
+    for i in range(3):
+        b.f[i] = 0x1000 * (i + 1)
+        b.phi[i] = 0x1000 * (i + 4)
+    h = ctypes.c_void_p()
+    p.dt = 4.0 * bound.value
+    rc = lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(h))
+    assert rc == binding.TLB_EUNSTABLE and h.value is None
+    assert b"stability bound" in lib.tlb_last_error()
+    # below the bound the strict flag lets validation through (creation then needs a GPU)
+    p.dt = 0.5 * bound.value
+    rc = lib.tlb_create_torus_grid(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(h))
+    assert rc != binding.TLB_EUNSTABLE
+    if h.value:
+        lib.tlb_destroy(h)
+
+
+def test_stable_dt_rejects_bad_arguments(lib):
+    out = ctypes.c_double()
+    assert lib.tlb_stable_dt(None, ctypes.byref(out)) == binding.TLB_EINVAL
+    p = params()
+    assert lib.tlb_stable_dt(ctypes.byref(p), None) == binding.TLB_EINVAL
+    p = params(r=-1.0)
+    assert lib.tlb_stable_dt(ctypes.byref(p), ctypes.byref(out)) == binding.TLB_EINVAL

@@ -165,3 +165,81 @@ def test_benchmark_ensemble_matches_grids_alone(torch_cuda):
     batch.close()
     for g in alone + batched:
         g.close()
+
+
+def mixed_ensemble(n, seed):
+    """n tori with different minor radii (0.6 .. 1.2), aspect ratios R/r in [1.5, 5], grid sizes
+    (some ragged: n_phi not a multiple of 64, n_theta not of the tile height) and time steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        r = float(rng.uniform(0.6, 1.2))
+        R = r * float(rng.uniform(1.5, 5.0))
+        nt = int(rng.choice([12, 24, 37, 64]))
+        np_ = int(rng.choice([40, 64, 96, 130, 200]))
+        dt = float(rng.uniform(1e-4, 2e-4))
+        out.append(inputs.TorusParams(r, R, nt, np_, 0.5, 2e-3, 0.05, 0.3, dt))
+    return out
+
+
+def test_batch_matches_oracle_fp64(torch_cuda):
+    """Each torus of a mixed ensemble stepped 70 times by tlb_batch_step_n (two replays of the
+    32-step batch graph and six single launches) against the CPU oracle stepping it alone:
+    f, phi, n and mu within 1e-12 relative, u within 1e-12 of the size of the terms it sums
+    (as in the single-grid parity tests)."""
+    from paper_1904_10070_amd import TorusBatch, TorusGrid
+    from tests.helpers import oracle_run, rel_linf, velocity_scale
+    params = mixed_ensemble(6, seed=31)
+    states = [inputs.random_state(p, seed=300 + i) for i, p in enumerate(params)]
+    grids = []
+    for p, st in zip(params, states):
+        g = TorusGrid(p, precision=64)
+        g.set_state(*st)
+        grids.append(g)
+    batch = TorusBatch(grids)
+    batch.step(70)
+    torch_cuda.cuda.synchronize()
+    for i, (p, st, g) in enumerate(zip(params, states, grids)):
+        og, f_ref, phi_ref = oracle_run(p, *st, 70)
+        f, ph = (x.cpu().numpy() for x in g.get_state())
+        mg = {k: v.cpu().numpy() for k, v in g.moments().items()}
+        mr = og.moments()
+        errs = {"f": rel_linf(f, f_ref), "phi": rel_linf(ph, phi_ref)}
+        for k in ("n", "mu"):
+            errs[k] = rel_linf(mg[k], mr[k])
+        for axis, k in enumerate(("u_theta", "u_phi")):
+            errs[k] = float(np.abs(mg[k] - mr[k]).max()) / velocity_scale(f_ref, mr["n"], axis)
+        print(f"torus {i}: r={p.r:.3f} R={p.R:.3f} {p.n_theta}x{p.n_phi} dt={p.dt:.2e}",
+              {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= 1e-12, (i, k, v)
+
+
+@pytest.mark.timeout(300)
+def test_benchmark_ensemble_fp32_matches_oracle(torch_cuda):
+    """The benchmark's 64-torus FP32 ensemble (3.1 GB of state copies: the streaming form of the
+    batched launch) after 2 batched steps, each torus against the FP64 oracle: within the FP32
+    rounding of two steps (the bar of the single-grid full-size test, 1e-5 relative)."""
+    from paper_1904_10070_amd import TorusBatch, TorusGrid
+    from tests.helpers import oracle_run, rel_linf
+    params = inputs.ensemble_workload()
+    grids, phis = [], []
+    for i, p in enumerate(params):
+        g = TorusGrid(p, precision=32)
+        phis.append(inputs.spinodal_phi(p, seed=1000 + i))
+        g.set_state(phis[-1], *inputs.rest_moments(p.n_theta, p.n_phi))
+        grids.append(g)
+    batch = TorusBatch(grids)
+    batch.autotune()
+    batch.step(2)
+    torch_cuda.cuda.synchronize()
+    worst = 0.0
+    for i, (p, g) in enumerate(zip(params, grids)):
+        _, f_ref, phi_ref = oracle_run(p, phis[i], *inputs.rest_moments(p.n_theta, p.n_phi), 2)
+        f, ph = (x.double().cpu().numpy() for x in g.get_state())
+        ef, ep = rel_linf(f, f_ref), rel_linf(ph, phi_ref)
+        worst = max(worst, ef, ep)
+        assert ef <= 1e-5 and ep <= 1e-5, (i, ef, ep)
+        g.close()
+    print(f"64-torus ensemble, 2 steps FP32 vs FP64 oracle: worst rel Linf {worst:.2e}",
+          flush=True)

@@ -234,3 +234,33 @@ def test_learned_step_graph_is_bitwise(torch_cuda):
         fb, pb = b.get_state()
         assert torch.equal(fa, fb) and torch.equal(pa, pb), call
         assert torch.isfinite(fa).all()
+
+
+def test_learned_step_graph_not_reused_by_a_new_grid(torch_cuda):
+    """The learned-step graph keeps the stage arguments of the grid it was built for.  A grid
+    created after that one was destroyed, on the very same state buffers (and often at the same
+    host address) but with another tau and dt, must not replay it: 40 learned steps of the new
+    grid equal 40 plain-launch steps (TLB_NO_GRAPH) of a grid with its parameters, bit for bit."""
+    torch = torch_cuda
+    from paper_1904_10070_amd import TorusGrid, NO_GRAPH
+    from paper_1904_10070_amd.binding import learned_step
+    p = inputs.TorusParams(1.0, 2.5, 16, 48, 0.5, 2e-3, 0.05, 0.3, 2e-4)
+    q = p.with_(tau=0.7, dt=1.5e-4)
+    phi, n, ut, up = inputs.random_state(p, seed=19)
+    params = (inputs.cnn_init_params(20) * 0.3).astype(np.float32)
+    net = make_net(torch, 16, 48, 1, params)
+    a = TorusGrid(p, 32)
+    a.set_state(phi, n, ut, up)
+    learned_step(a, net, 40)                    # builds the graph for grid a
+    bufs = (a.f, a.phi)
+    a.close()
+    b = TorusGrid(q, 32, buffers=bufs)          # same buffers, other parameters
+    b.set_state(phi, n, ut, up)
+    learned_step(b, net, 40)
+    c = TorusGrid(q.with_(flags=NO_GRAPH), 32)
+    c.set_state(phi, n, ut, up)
+    learned_step(c, net, 40)
+    torch.cuda.synchronize()
+    fb, pb = b.get_state()
+    fc, pc = c.get_state()
+    assert torch.equal(fb, fc) and torch.equal(pb, pc)
