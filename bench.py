@@ -90,9 +90,11 @@ def leg_result(p, precision, ts_per_step, steps):
                         "ms_per_step_max": st["max"] * 1e3, "spread": st["spread"]})
 
 
-def gpu_leg(p, precision, steps, warmup, seed=7, phi=None):
+def gpu_leg(p, precision, steps, warmup, seed=7, phi=None, rows=None):
     """`warmup` untimed steps, then REPS timed repetitions of exactly `steps` steps."""
     g = new_grid(p, precision, seed, phi)
+    if rows:
+        g.set_tile_rows(rows)
     g.step(warmup)
     ts = [t / steps for t in event_reps(lambda: g.step(steps), g.stream)]
     bad = g.invariants()[2]
@@ -404,6 +406,9 @@ def main():
                                        "ensemble32", "learned32", "learnedstep32", "train32",
                                        "weno32", "stream"],
                     help="time a single workload/precision (profiling runs)")
+    ap.add_argument("--rows", type=int, choices=[4, 8, 16],
+                    help="tile height of the stage kernel for --only legs (default: the "
+                         "library's 8)")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="run only the project's copy kernel on MIB mebibytes, 20 times (the "
                          "reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -450,8 +455,9 @@ def main():
         p = inputs.spinodal_workload(0.6) if wl in ("spinodal", "weno") else inputs.roofline_workload()
         if wl == "weno":
             p = p.with_(flags=WENO5)
-        d = gpu_leg(p, prec, args.steps, args.warmup)
+        d = gpu_leg(p, prec, args.steps, args.warmup, rows=args.rows)
         print(json.dumps({"workload": f"{wl} {p.n_theta}x{p.n_phi}", "precision": prec,
+                          "rows": args.rows or 8,
                           "value": d["nups"], "unit": "node-updates/s",
                           "ms_per_step": d["t_step"] * 1e3, "achieved_gbs": d["achieved_gbs"],
                           "roofline_frac": d["achieved_gbs"] / HBM_PEAK_GBS,

@@ -4,13 +4,14 @@
 //
 // One time step = three launches of one fused stage kernel (three-stage SSP Runge-Kutta).
 // Each launch evaluates the whole right-hand side of the semi-discrete system for a tile of
-// 64 (phi) x 4 (theta) nodes and writes the Runge-Kutta combination:
-//   * order parameter tile with a 2-node halo -> LDS; chemical potential mu (eq. mu, with the
-//     surface Laplace-Beltrami operator) on the tile and its cross-shaped 1-node ring -> LDS;
-//   * the 16 populations stream one at a time through a double-buffered LDS tile with a
-//     3-node halo: each thread keeps its node's f_k and accumulates the upwind (UW5) flux
-//     difference along phi and theta (eq. boltz_tor advection, metric factors r and J);
-//     threads owning a ring node accumulate that node's moments for the CH flux;
+// 64 (phi) x TY (theta, 4, 8 or 16) nodes and writes the Runge-Kutta combination:
+//   * the 16 populations stream, two at a time, through a ring of LDS tiles with a 3-node
+//     halo filled by asynchronous copies: each thread keeps its node's f_k and accumulates the
+//     upwind (UW5) flux difference along phi and theta (eq. boltz_tor advection, metric factors
+//     r and J); threads owning a ring node accumulate that node's moments for the CH flux;
+//   * order parameter tile with a 2-node halo -> LDS (copied ahead of the populations);
+//     chemical potential mu (eq. mu, with the surface Laplace-Beltrami operator) on the tile
+//     and its cross-shaped 1-node ring -> LDS;
 //   * per node: moments, f_eq (eq. feq), BGK, the velocity-space force and connection terms
 //     through the K^H matrix (section II C), the phi grad mu interface force (eq. pbin), the
 //     Cahn-Hilliard right-hand side (eq. CH), and the Runge-Kutta combine -> coalesced stores.
@@ -329,9 +330,9 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
   return A * ph * (ph * ph - T(1)) - kappa * lap;
 }
 
-// population ring depth: copies of up to RING-1 populations are in flight while one is used
-// y^n of the node (stages 2 and 3) is loaded during the population loop instead of in the
-// epilogue, which hides its latency; costs 16 (FP32) or 32 (FP64) VGPRs
+// population ring depth D: while a group of PB populations is used, the copies of the next
+// D - PB are in flight.  y^n of the node (stages 2 and 3) is loaded during the population loop
+// instead of in the epilogue, which hides its latency; costs 16 (FP32) or 32 (FP64) VGPRs
 #ifndef TLB_PREFETCH_Y0_32
 #define TLB_PREFETCH_Y0_32 1
 #endif
@@ -339,7 +340,7 @@ __device__ __forceinline__ T mu_at(const T* sPhi, int y, int x, const RowCoef<T>
 #define TLB_PREFETCH_Y0_64 0
 #endif
 #ifndef TLB_RING32
-#define TLB_RING32 4
+#define TLB_RING32 6
 #endif
 #ifndef TLB_RING64
 #define TLB_RING64 6
@@ -381,10 +382,47 @@ __device__ __forceinline__ T get_y0(const T* p) {
     return *p;
 }
 
+// Populations are consumed in groups of PB: one wait and one block barrier per group, after
+// which the ring slots of the previous group are refilled with populations k+D-PB .. k+D-1.
+// ops_after_copy: the vector-memory instructions a wave issues after the copy of population m
+// and before the wait of the group starting at population k, which may still be outstanding
+// when population m has landed (vmcnt counts in issue order).  Issue order: the
+// order-parameter copy, populations 0..D-1 (DW instructions each), the phi^n load (Y0), then
+// in group k the refill copies followed by the y^n loads of the group's populations (Y0).
+template <int D, int DW, bool Y0, int PB>
+__host__ __device__ constexpr int ops_after_copy(int m, int k) {
+  int count = 0;
+  bool seen = false;
+  for (int p = 0; p < D; ++p) {
+    if (seen) count += DW;
+    if (p == m) seen = true;
+  }
+  if (Y0 && seen) count += 1;
+  for (int g = 0; g < k; g += PB) {
+    if (g >= PB)
+      for (int p = g + D - PB; p < g + D && p < 16; ++p) {
+        if (seen) count += DW;
+        if (p == m) seen = true;
+      }
+    if (Y0 && seen) count += PB;
+  }
+  return count;
+}
+
+// populations consumed per block barrier (a sweep of 1, 2 and 4 with ring depths 4-8 on both
+// precisions: 2 with depth 6 is fastest, by 0.4-2 %)
+#ifndef TLB_GROUP32
+#define TLB_GROUP32 2
+#endif
+#ifndef TLB_GROUP64
+#define TLB_GROUP64 2
+#endif
 template <typename T>
 struct Ring {
   static constexpr int D = sizeof(T) == 4 ? TLB_RING32 : TLB_RING64;
+  static constexpr int PB = sizeof(T) == 4 ? TLB_GROUP32 : TLB_GROUP64;  // populations per barrier
   static constexpr bool PREFETCH = sizeof(T) == 4 ? TLB_PREFETCH_Y0_32 : TLB_PREFETCH_Y0_64;
+  static_assert(D % PB == 0 && 16 % PB == 0 && D > PB, "ring depth and group size");
 };
 
 // One right-hand-side evaluation + Runge-Kutta combine for the tile (tx, ty) of the grid
@@ -464,14 +502,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   if (!ring) { ry = 0; rx = 0; }
   const RowCoef<T>& rrc = a.rows[wrapi(q0 + ry, nt)];
 
-  // order parameter copies done (the D population tiles may still be in flight)
+  // The order-parameter tile is read only after the population loop (chemical potential,
+  // force, Cahn-Hilliard): the loop's first wait covers its copy, which was issued first, and
+  // reading it here would make the compiler drain every copy in flight before the loop.
   static_assert(CopyPhi::INSTR + DW * D < 64, "outstanding copies exceed the vmcnt range");
-  wait_vm_lgkm0<DW * D>();
-  __builtin_amdgcn_s_barrier();
-
-  // ---- chemical potential on the tile and the ring
-  sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
-  if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
 
   // ---- stream the 16 populations through the LDS ring
   T f[16], adv[16];
@@ -505,18 +539,33 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int i = k >> 2, j = k & 3;
-    // populations issued before this point: D by the prologue, one more by each iteration
-    // 1..k-1 (capped at 16); wait until population k has landed
-    constexpr int issued_raw = k + D - 1 > D ? k + D - 1 : D;
-    constexpr int issued = issued_raw < 16 ? issued_raw : 16;
-    wait_vm_lgkm0<DW * (issued - k - 1)>();
-    __builtin_amdgcn_s_barrier();
-    // every wave is past population k-1: its ring slot can be refilled
-    if constexpr (k >= 1 && k + D - 1 < 16)
-      cp_f.issue(a.fin + (k + D - 1) * a.plane, plane_bytes, slot(ic<k + D - 1>{}), wave);
+    constexpr int PB = Ring<T>::PB;
+    if constexpr (k % PB == 0) {
+      // wait until populations k .. k+PB-1 have landed: at most the vector-memory instructions
+      // issued after the last one's copy may be outstanding (in FP32 stages with y^n these
+      // include the y^n loads)
+      constexpr int m = k + PB - 1;
+      if constexpr (PF) {
+        if (a.has_y0) wait_vm_lgkm0<ops_after_copy<D, DW, true, PB>(m, k)>();
+        else wait_vm_lgkm0<ops_after_copy<D, DW, false, PB>(m, k)>();
+      } else {
+        wait_vm_lgkm0<ops_after_copy<D, DW, false, PB>(m, k)>();
+      }
+      __builtin_amdgcn_s_barrier();
+      // every wave is past populations k-PB .. k-1: their ring slots can be refilled
+      if constexpr (k >= PB)
+        static_for<k + D - PB, (k + D < 16 ? k + D : 16)>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          cp_f.issue(a.fin + p * a.plane, plane_bytes, slot(ic<p>{}), wave);
+        });
+      if constexpr (PF)
+        if (a.has_y0)
+          static_for<k, k + PB>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            yn[p] = get_y0<STREAM>(at_node(a.f0, p * a.plane + row0, lane_bytes));
+          });
+    }
     const T* buf = slot(ic<k>{});
-    if constexpr (PF)
-      if (a.has_y0) yn[k] = get_y0<STREAM>(at_node(a.f0, k * a.plane + row0, lane_bytes));
     f[k] = buf[cN];
     n += f[k];
     nut += T(vel(i)) * f[k];
@@ -576,6 +625,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     pin_reg(rut);
     pin_reg(rup);
   });
+
+  // ---- chemical potential on the tile and the ring (the order-parameter tile has landed:
+  //      its copy was issued before population 0's)
+  sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
+  if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
 
   // ---- CH fluxes of the tile and the ring
   // with deviation storage the sums above are n - n_ref; dn keeps that small difference
@@ -684,9 +738,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
 #endif
 }
 
+// Minimum waves per SIMD the compiler is asked to keep room for (register budget 512 / waves
+// VGPRs); 1 leaves the allocation free.
+#ifndef TLB_WPE32
+#define TLB_WPE32 1
+#endif
+#ifndef TLB_WPE64
+#define TLB_WPE64 1
+#endif
+template <typename T>
+struct StageWaves {
+  static constexpr int value = sizeof(T) == 4 ? TLB_WPE32 : TLB_WPE64;
+};
+
 template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false,
           bool GENREF = false>
-__global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a) {
+__global__ __launch_bounds__(Tile<TY>::NT) __attribute__((amdgpu_waves_per_eu(
+    StageWaves<T>::value))) void tlb_stage_kernel(StageArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   int tx, ty;
   band_tile(tile, a.ntx, a.nty, tx, ty);
@@ -698,7 +766,8 @@ __global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_kernel(StageArgs<T> a)
 // tile order (tile_begin[n] = total).  XCD x owns a contiguous range of that order, which its
 // gridDim.x / 8 resident blocks walk with a stride, tile by tile.
 template <typename T, bool VEC, int TY, bool GENREF = false, bool STREAM = false>
-__global__ __launch_bounds__(Tile<TY>::NT) void tlb_stage_batch_kernel(
+__global__ __launch_bounds__(Tile<TY>::NT) __attribute__((amdgpu_waves_per_eu(
+    StageWaves<T>::value))) void tlb_stage_batch_kernel(
     const StageArgs<T>* __restrict__ table, const int* __restrict__ tile_begin, int n, int stage) {
   const int total = tile_begin[n];
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = gridDim.x >> 3;
