@@ -196,6 +196,17 @@ int32_t tlb_diagnostics(tlb_grid* grid, double out[2], double* phi_avg, double* 
  * TLB_ENOMEM, TLB_EHIP.                                                                    */
 int32_t tlb_structure_length(tlb_grid* grid, double out[3]);
 
+/* tlb_structure_length without any allocation, for callers that cannot allocate device
+ * memory (serving loops, code that must not call hipMalloc): the same outputs (to rounding:
+ * its twiddle factors are computed on the GPU and its final sums are taken in another fixed
+ * order) from a workspace that is a static device array of 24 MiB per GPU, held from the
+ * library's first use on that GPU until the process ends; nothing is allocated, on the device
+ * or the host.  Grids need (n_theta n_phi + n_theta + n_phi) 16 + 16 n_phi + 24 bytes of it
+ * (up to about 1.5 M nodes); larger grids get TLB_EINVAL.  Every call on one GPU uses the same
+ * workspace, which keeps the last call's contents: calls that overlap on one GPU (on several
+ * streams or host threads) race.  Waits for the grid's stream.  Errors: TLB_EINVAL, TLB_EHIP. */
+int32_t tlb_structure_length_noalloc(tlb_grid* grid, double out[3]);
+
 /* Release the handle and the library's own device memory (not the caller's buffers).      */
 void tlb_destroy(tlb_grid* grid);
 

@@ -29,6 +29,7 @@ EXPORTED = ("tlb_stable_dt", "tlb_create_torus_grid", "tlb_set_state", "tlb_step
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",
             "tlb_last_error", "tlb_set_tile_rows", "tlb_autotune", "tlb_create_batch",
             "tlb_batch_step_n", "tlb_batch_autotune", "tlb_destroy_batch", "tlb_structure_length",
+            "tlb_structure_length_noalloc",
             "tlb_cnn_create", "tlb_cnn_destroy", "tlb_cnn_set_params", "tlb_cnn_get_params",
             "tlb_cnn_forward", "tlb_cnn_gradient", "tlb_cnn_train_step", "tlb_learn_stats",
             "tlb_restrict", "tlb_learn_pair", "tlb_apply_correction", "tlb_learned_step_n",
@@ -103,6 +104,8 @@ def load_library(path=None):
     lib.tlb_diagnostics.restype = i32
     lib.tlb_structure_length.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.tlb_structure_length.restype = i32
+    lib.tlb_structure_length_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.tlb_structure_length_noalloc.restype = i32
     lib.tlb_set_tile_rows.argtypes = [vp, i32]
     lib.tlb_set_tile_rows.restype = i32
     lib.tlb_autotune.argtypes = [vp, ctypes.POINTER(i32)]
@@ -287,6 +290,13 @@ class TorusGrid:
         """(L_S, sum S, sum |k| S) of phi: the structure-factor coarsening length."""
         out = (ctypes.c_double * 3)()
         _check(self.lib, self.lib.tlb_structure_length(self._h, out), "tlb_structure_length")
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def structure_length_noalloc(self):
+        """structure_length() through tlb_structure_length_noalloc (no allocation)."""
+        out = (ctypes.c_double * 3)()
+        _check(self.lib, self.lib.tlb_structure_length_noalloc(self._h, out),
+               "tlb_structure_length_noalloc")
         return float(out[0]), float(out[1]), float(out[2])
 
     def set_tile_rows(self, rows):

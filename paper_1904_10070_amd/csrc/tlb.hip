@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -45,10 +46,24 @@ namespace {
 // ------------------------------------------------------------------------------------------
 // error reporting
 thread_local std::string g_last_error;
+// a message in static storage, set instead of g_last_error by the entry point that allocates
+// nothing (assigning a std::string may allocate)
+thread_local const char* g_static_error = nullptr;
 
 int32_t fail(int32_t code, const std::string& msg) {
+  g_static_error = nullptr;
   g_last_error = msg;
   return code;
+}
+
+int32_t fail_static(int32_t code, const char* msg) {
+  g_static_error = msg;
+  return code;
+}
+
+void clear_error() {
+  g_last_error.clear();  // keeps its capacity: no allocation
+  g_static_error = nullptr;
 }
 
 #define TLB_HIP_CHECK(call)                                                              \
@@ -1765,21 +1780,140 @@ int32_t structure_t(tlb_grid* g, double out[3]) {
   return TLB_OK;
 }
 
+// ---- the structure-factor length without allocation (tlb_structure_length_noalloc)
+//
+// Its workspace is `scratch`, a device array of this file: one copy per GPU, kept until the
+// process ends, shared by every call on that GPU (calls that overlap on one GPU race).  Host
+// code never passes `scratch` itself (the name stands for a host-side shadow): the device
+// address of each GPU's copy is taken once per device with hipGetSymbolAddress and kept.
+// Layout: X [nt][np] complex, twiddles (np + nt) complex, partials 2 np doubles, 3 results.
+constexpr size_t SCRATCH_BYTES = size_t(24) << 20;
+__device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+size_t scratch_need(int nt, int np) {
+  return ((size_t)nt * np + (size_t)np + nt) * sizeof(double2) + 2 * (size_t)np * sizeof(double) +
+         3 * sizeof(double);
+}
+
+// the device address of the current device's `scratch` (looked up on its first use)
+int32_t scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess)
+    return fail_static(TLB_EHIP, "structure factor (no allocation): hipGetDevice failed");
+  if (dev < 0 || dev >= SCRATCH_DEVICES)
+    return fail_static(TLB_EHIP, "structure factor (no allocation): device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return fail_static(TLB_EHIP, "structure factor (no allocation): hipGetSymbolAddress failed");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TLB_OK;
+}
+
+// exp(-2 pi i j / n) for j < np (row transform) followed by the same for the column length nt
+__global__ __launch_bounds__(RED_THREADS) void tlb_twiddle_kernel(double2* tw, int np, int nt) {
+  const int j = blockIdx.x * RED_THREADS + threadIdx.x;
+  if (j >= np + nt) return;
+  const int n = j < np ? np : nt, m = j < np ? j : j - np;
+  double sn, cs;
+  sincospi(2.0 * m / n, &sn, &cs);
+  tw[j] = make_double2(cs, -sn);
+}
+
+// sums of the per-mode partials in a fixed order and L_S = 2 pi sum S / sum |k| S
+__global__ __launch_bounds__(RED_THREADS) void tlb_structure_final_kernel(const double* part,
+                                                                         int np, double* out) {
+  __shared__ double sh[2][RED_THREADS / 64];
+  double s0 = 0.0, s1 = 0.0;
+  for (int mp = threadIdx.x; mp < np; mp += RED_THREADS) {
+    s0 += part[2 * mp];
+    s1 += part[2 * mp + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = s0;
+    sh[1][w] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < RED_THREADS / 64; ++i) {
+      a += sh[0][i];
+      b += sh[1][i];
+    }
+    out[0] = b > 0.0 ? 2.0 * M_PI * a / b : INFINITY;
+    out[1] = a;
+    out[2] = b;
+  }
+}
+
+template <typename T>
+int32_t structure_noalloc_t(tlb_grid* g, double out[3]) {
+  const int nt = g->p.n_theta, np = g->p.n_phi;
+  if ((size_t)np * sizeof(double) > 64 * 1024 || (size_t)nt * sizeof(double2) > 64 * 1024)
+    return fail_static(TLB_EINVAL,
+                       "structure factor: a row or column exceeds the 64 KB of LDS per block");
+  if (scratch_need(nt, np) > SCRATCH_BYTES)
+    return fail_static(TLB_EINVAL,
+                       "structure factor (no allocation): grid too large for the 24 MiB "
+                       "workspace ((n_theta n_phi + n_theta + n_phi) 16 + n_phi 16 + 24 bytes)");
+  void* base = nullptr;
+  int32_t rc = scratch_address(&base);
+  if (rc != TLB_OK) return rc;
+  double2* X = static_cast<double2*>(base);
+  double2* tw = X + (size_t)nt * np;
+  double* part = reinterpret_cast<double*>(tw + np + nt);
+  double* res = part + 2 * (size_t)np;
+  hipLaunchKernelGGL(tlb_twiddle_kernel, dim3((np + nt + RED_THREADS - 1) / RED_THREADS),
+                     dim3(RED_THREADS), 0, g->stream, tw, np, nt);
+  hipLaunchKernelGGL(tlb_dft_rows_kernel<T>, dim3(nt), dim3(RED_THREADS), np * sizeof(double),
+                     g->stream, static_cast<const T*>(g->phi[0]), tw, X, np);
+  hipLaunchKernelGGL(tlb_dft_cols_kernel, dim3(np), dim3(RED_THREADS), nt * sizeof(double2),
+                     g->stream, X, tw + np, nt, np, g->p.r, g->p.R, part);
+  hipLaunchKernelGGL(tlb_structure_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream, part,
+                     np, res);
+  if (hipGetLastError() != hipSuccess)
+    return fail_static(TLB_EHIP, "structure factor (no allocation): kernel launch failed");
+  if (hipMemcpyAsync(out, res, 3 * sizeof(double), hipMemcpyDeviceToHost, g->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(g->stream) != hipSuccess)
+    return fail_static(TLB_EHIP, "structure factor (no allocation): copy of the result failed");
+  return TLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* tlb_last_error(void) { return g_last_error.c_str(); }
+int32_t tlb_structure_length_noalloc(tlb_grid* g, double out[3]) {
+  clear_error();
+  if (!g || !out) return fail_static(TLB_EINVAL, "grid or out is NULL");
+  return g->p.precision == 64 ? structure_noalloc_t<double>(g, out)
+                              : structure_noalloc_t<float>(g, out);
+}
+
+const char* tlb_last_error(void) {
+  return g_static_error ? g_static_error : g_last_error.c_str();
+}
 
 int32_t tlb_structure_length(tlb_grid* g, double out[3]) {
-  g_last_error.clear();
+  clear_error();
   if (!g || !out) return fail(TLB_EINVAL, "grid or out is NULL");
   return g->p.precision == 64 ? structure_t<double>(g, out) : structure_t<float>(g, out);
 }
 
 int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffers,
                               void* hip_stream, tlb_grid** out) {
-  g_last_error.clear();
+  clear_error();
   if (!out) return fail(TLB_EINVAL, "out is NULL");
   *out = nullptr;
   int32_t rc = check_params(params);
@@ -1877,7 +2011,7 @@ void tlb_destroy(tlb_grid* g) {
 
 int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n,
                       const void* ut, const void* up) {
-  g_last_error.clear();
+  clear_error();
   if (!g || !phi) return fail(TLB_EINVAL, "grid or phi is NULL");
   if (!f && (!n || !ut || !up)) return fail(TLB_EINVAL, "f is NULL and a moment field is NULL");
   const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
@@ -1906,7 +2040,7 @@ int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n
 }
 
 int32_t tlb_stable_dt(const tlb_params* params, double* dt_max) {
-  g_last_error.clear();
+  clear_error();
   if (!dt_max) return fail(TLB_EINVAL, "dt_max is NULL");
   if (!params) return fail(TLB_EINVAL, "params is NULL");
   tlb_params p = *params;
@@ -1918,7 +2052,7 @@ int32_t tlb_stable_dt(const tlb_params* params, double* dt_max) {
 }
 
 int32_t tlb_step_n(tlb_grid* g, int64_t n_steps) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
   const bool dbl = g->p.precision == 64;
@@ -1945,14 +2079,14 @@ int32_t tlb_step_n(tlb_grid* g, int64_t n_steps) {
 }
 
 int32_t tlb_get_moments(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   return g->p.precision == 64 ? moments_t<double>(g, n, ut, up, phi, mu)
                               : moments_t<float>(g, n, ut, up, phi, mu);
 }
 
 int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
   if (f) {
@@ -1970,7 +2104,7 @@ int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
 }
 
 int32_t tlb_invariants(tlb_grid* g, double out[3]) {
-  g_last_error.clear();
+  clear_error();
   if (!g || !out) return fail(TLB_EINVAL, "grid or out is NULL");
   int32_t rc = g->p.precision == 64 ? reduce_t<double>(g, 0.0) : reduce_t<float>(g, g->n_ref);
   if (rc != TLB_OK) return rc;
@@ -1982,7 +2116,7 @@ int32_t tlb_invariants(tlb_grid* g, double out[3]) {
 }
 
 int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (rows != 4 && rows != 8 && rows != 16) return fail(TLB_EINVAL, "tile rows must be 4, 8 or 16");
   if ((g->p.flags & TLB_WENO5) && rows != DEFAULT_TY)
@@ -1995,7 +2129,7 @@ int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
 }
 
 int32_t tlb_autotune(tlb_grid* g, int32_t* rows) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (g->p.flags & TLB_WENO5) {  // one tile height only
     if (rows) *rows = g->ty;
@@ -2005,7 +2139,7 @@ int32_t tlb_autotune(tlb_grid* g, int32_t* rows) {
 }
 
 int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tlb_batch** out) {
-  g_last_error.clear();
+  clear_error();
   if (!out) return fail(TLB_EINVAL, "out is NULL");
   *out = nullptr;
   if (!grids || n < 1) return fail(TLB_EINVAL, "a batch needs at least one grid");
@@ -2060,7 +2194,7 @@ int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tl
 }
 
 int32_t tlb_batch_step_n(tlb_batch* b, int64_t n_steps) {
-  g_last_error.clear();
+  clear_error();
   if (!b) return fail(TLB_EINVAL, "batch is NULL");
   if (n_steps < 0) return fail(TLB_EINVAL, "n_steps < 0");
   // a grid whose stage arguments changed since the table was built (a new reference density)
@@ -2074,7 +2208,7 @@ int32_t tlb_batch_step_n(tlb_batch* b, int64_t n_steps) {
 }
 
 int32_t tlb_batch_autotune(tlb_batch* b, int32_t* rows) {
-  g_last_error.clear();
+  clear_error();
   if (!b) return fail(TLB_EINVAL, "batch is NULL");
   return b->precision == 64 ? batch_autotune_t<double>(b, rows) : batch_autotune_t<float>(b, rows);
 }
@@ -2091,7 +2225,7 @@ void tlb_destroy_batch(tlb_batch* b) {
 }
 
 int32_t tlb_diagnostics(tlb_grid* g, double out[2], double* phi_avg, double* p_avg) {
-  g_last_error.clear();
+  clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   int32_t rc = g->p.precision == 64 ? diag_t<double>(g, phi_avg, p_avg)
                                     : diag_t<float>(g, phi_avg, p_avg);

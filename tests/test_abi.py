@@ -85,6 +85,8 @@ def test_null_handles_rejected(lib):
     assert lib.tlb_invariants(None, out) == binding.TLB_EINVAL
     assert lib.tlb_diagnostics(None, out, None, None) == binding.TLB_EINVAL
     assert lib.tlb_structure_length(None, out) == binding.TLB_EINVAL
+    assert lib.tlb_structure_length_noalloc(None, out) == binding.TLB_EINVAL
+    assert b"NULL" in lib.tlb_last_error()
     assert lib.tlb_set_tile_rows(None, 8) == binding.TLB_EINVAL
     assert lib.tlb_autotune(None, None) == binding.TLB_EINVAL
     assert lib.tlb_batch_step_n(None, 1) == binding.TLB_EINVAL
