@@ -18,6 +18,7 @@ from . import build as _build
 FLAT = 1
 CH_NO_ADVECTION = 2
 WENO5 = 8
+CH4 = 32
 
 _DP = ctypes.POINTER(ctypes.c_double)
 

@@ -26,7 +26,10 @@
  *     face values by the fifth-order upwind (UW5) linear reconstruction, upwind by sign(v);
  *     with TLBREF_WENO5 the same faces by the nonlinear WENO-5 reconstruction of Jiang and
  *     Shu (J. Comput. Phys. 126, 1996), whose weights reduce to the UW5 ones on smooth data;
- *   - Cahn-Hilliard: second-order central flux form with face averages;
+ *   - Cahn-Hilliard: second-order central flux form with face averages; with TLBREF_CH4 the
+ *     same equation at fourth order (surface Laplacian in conservative staggered form along
+ *     theta and the five-point fourth-order difference along phi, fourth-order central flux
+ *     differences for the advection and for grad mu in the force);
  *   - time stepping: three-stage strong-stability-preserving Runge-Kutta (Shu-Osher form) on
  *     the joint state (f, phi);
  *   - interface force in the potential form n F = -phi grad mu, central differences;
@@ -47,6 +50,7 @@ typedef TLBREF_REAL real;
 #define TLBREF_FLAT 1u            /* J = R, G = 0: the flat periodic Cartesian limit        */
 #define TLBREF_CH_NO_ADVECTION 2u /* drop the u phi flux from Cahn-Hilliard                */
 #define TLBREF_WENO5 8u           /* face values by the nonlinear WENO-5 reconstruction     */
+#define TLBREF_CH4 32u            /* fourth-order Cahn-Hilliard discretisation (see rhs)    */
 #define TLBREF_WENO_EPS 1e-6      /* the smoothness regulariser of Jiang and Shu            */
 
 #define TLBREF_OK 0
@@ -173,12 +177,55 @@ static real face_value(int weno, real hm2, real hm1, real h0, real hp1, real hp2
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Fourth-order Cahn-Hilliard operators (TLBREF_CH4).
+ *
+ * Surface Laplace-Beltrami operator Delta_S h = 1/(r^2 J) d_theta (J d_theta h)
+ * + 1/J^2 d_phi^2 h:
+ *   along theta, the gradient at the face theta_{q+1/2} to fourth order,
+ *     (h_{q-1} - 27 h_q + 27 h_{q+1} - h_{q+2}) / (24 dtheta),
+ *   times J at that face, and the derivative of those face fluxes at the node to fourth order,
+ *     (F_{q-3/2} - 27 F_{q-1/2} + 27 F_{q+1/2} - F_{q+3/2}) / (24 dtheta);
+ *   it is a difference of the face quantities (-F_{q+3/2} + 26 F_{q+1/2} - F_{q-1/2}) / 24, so
+ *   sum_q J_q Delta_S h telescopes to zero (conservation);
+ *   along phi (J constant), the fourth-order second difference
+ *     (-h_{s-2} + 16 h_{s-1} - 30 h_s + 16 h_{s+1} - h_{s+2}) / (12 dphi^2),
+ *   the difference of the face quantities (h_{s-1} - 15 h_s + 15 h_{s+1} - h_{s+2}) / 12.
+ * First derivatives (the advection divergence and grad mu): the fourth-order central
+ * difference (h_{q-2} - 8 h_{q-1} + 8 h_{q+1} - h_{q+2}) / (12 d), which is the difference of
+ * the face values (-h_{q-1} + 7 h_q + 7 h_{q+1} - h_{q+2}) / 12 (conservative flux form).     */
+static real grad4_face_theta(const tlbref_grid* g, const real* h, int qa, int s) {
+  const int nt = g->nt;
+  return (h[IDX(g, wrap(qa - 1, nt), s)] - RC(27) * h[IDX(g, wrap(qa, nt), s)] +
+          RC(27) * h[IDX(g, wrap(qa + 1, nt), s)] - h[IDX(g, wrap(qa + 2, nt), s)]) /
+         (RC(24) * g->dth);
+}
+
+static real lap4(const tlbref_grid* g, const real* h, int q, int s) {
+  const int nt = g->nt, np = g->np;
+  real F[4]; /* J times the face gradient at theta_{q-3/2}, _{q-1/2}, _{q+1/2}, _{q+3/2} */
+  for (int m = -2; m <= 1; ++m) F[m + 2] = g->Jp[wrap(q + m, nt)] * grad4_face_theta(g, h, q + m, s);
+  real lap_th = (F[0] - RC(27) * F[1] + RC(27) * F[2] - F[3]) / (RC(24) * g->dth) /
+                (g->r * g->r * g->J[q]);
+  real lap_ph = (-h[IDX(g, q, wrap(s - 2, np))] + RC(16) * h[IDX(g, q, wrap(s - 1, np))] -
+                 RC(30) * h[IDX(g, q, s)] + RC(16) * h[IDX(g, q, wrap(s + 1, np))] -
+                 h[IDX(g, q, wrap(s + 2, np))]) /
+                (RC(12) * g->dph * g->dph * g->J[q] * g->J[q]);
+  return lap_th + lap_ph;
+}
+
+/* fourth-order conservative face value (-h_{-1} + 7 h_0 + 7 h_1 - h_2) / 12 */
+static real face4(real hm1, real h0, real hp1, real hp2) {
+  return (-hm1 + RC(7) * h0 + RC(7) * hp1 - hp2) / RC(12);
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* One evaluation of the right-hand side L(f, phi) of the semi-discrete system.                */
 static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* Lphi) {
   const int nt = g->nt, np = g->np;
   const real r = g->r, dth = g->dth, dph = g->dph;
   const real A = g->A, kappa = g->kappa, M = g->M, tau = g->tau;
   const int ch_adv = !(g->p.flags & TLBREF_CH_NO_ADVECTION);
+  const int ch4 = (g->p.flags & TLBREF_CH4) != 0;
 
   /* 1. moments n = sum f, n u = sum f v (section II C) */
 #pragma omp parallel for schedule(static)
@@ -212,7 +259,7 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
       real lap_th = (flux_up - flux_dn) / (r * r * g->J[q] * dth);
       real lap_ph = (phi[IDX(g, q, sp)] - RC(2) * ph + phi[IDX(g, q, sm)]) /
                     (g->J[q] * g->J[q] * dph * dph);
-      real lap = lap_th + lap_ph;
+      real lap = ch4 ? lap4(g, phi, q, s) : lap_th + lap_ph;
       g->lap[IDX(g, q, s)] = lap;
       g->mu[IDX(g, q, s)] = -A * ph * (RC(1) - ph * ph) - kappa * lap;
     }
@@ -232,6 +279,15 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
       real ph = phi[c], n = g->n[c];
       real dmu_th = (g->mu[IDX(g, qp, s)] - g->mu[IDX(g, qm, s)]) / (RC(2) * r * dth);
       real dmu_ph = (g->mu[IDX(g, q, sp)] - g->mu[IDX(g, q, sm)]) / (RC(2) * g->J[q] * dph);
+      if (ch4) {
+        int q2p = wrap(q + 2, nt), q2m = wrap(q - 2, nt), s2p = wrap(s + 2, np), s2m = wrap(s - 2, np);
+        dmu_th = (g->mu[IDX(g, q2m, s)] - RC(8) * g->mu[IDX(g, qm, s)] +
+                  RC(8) * g->mu[IDX(g, qp, s)] - g->mu[IDX(g, q2p, s)]) /
+                 (RC(12) * r * dth);
+        dmu_ph = (g->mu[IDX(g, q, s2m)] - RC(8) * g->mu[IDX(g, q, sm)] +
+                  RC(8) * g->mu[IDX(g, q, sp)] - g->mu[IDX(g, q, s2p)]) /
+                 (RC(12) * g->J[q] * dph);
+      }
       g->Fth[c] = -ph * dmu_th / n;
       g->Fph[c] = -ph * dmu_ph / n;
 
@@ -242,8 +298,20 @@ static void rhs(tlbref_grid* g, const real* f, const real* phi, real* Lf, real* 
       real lapmu = (fu - fd) / (r * r * g->J[q] * dth) +
                    (g->mu[IDX(g, q, sp)] - RC(2) * mu0 + g->mu[IDX(g, q, sm)]) /
                        (g->J[q] * g->J[q] * dph * dph);
+      if (ch4) lapmu = lap4(g, g->mu, q, s);
       real adv = RC(0);
-      if (ch_adv) {
+      if (ch_adv && ch4) {
+        /* theta: nodal flux J u^theta phi, phi: u^phi phi, fourth-order face values */
+        real P[5], Q[5];
+        for (int o = -2; o <= 2; ++o) {
+          size_t cq = IDX(g, wrap(q + o, nt), s), cs = IDX(g, q, wrap(s + o, np));
+          P[o + 2] = g->J[wrap(q + o, nt)] * g->ut[cq] * phi[cq];
+          Q[o + 2] = g->up[cs] * phi[cs];
+        }
+        real face_n = face4(P[1], P[2], P[3], P[4]), face_s = face4(P[0], P[1], P[2], P[3]);
+        real face_e = face4(Q[1], Q[2], Q[3], Q[4]), face_w = face4(Q[0], Q[1], Q[2], Q[3]);
+        adv = (face_n - face_s) / (r * g->J[q] * dth) + (face_e - face_w) / (g->J[q] * dph);
+      } else if (ch_adv) {
         /* theta faces carry J u^theta phi, phi faces carry u^phi phi */
         real Pc = g->J[q] * g->ut[c] * ph;
         real Pn = g->J[qp] * g->ut[IDX(g, qp, s)] * phi[IDX(g, qp, s)];
