@@ -71,6 +71,13 @@ extern "C" {
                                 * one; tiles of 8 rows only, not in batches                   */
 #define TLB_STRICT_DT 16u      /* tlb_create_torus_grid refuses (TLB_EUNSTABLE) a dt above the *
                                 * bound of tlb_stable_dt                                       */
+#define TLB_CH4 32u            /* Cahn-Hilliard at fourth order: the surface Laplacian of mu   *
+                                * and of M mu in conservative staggered form along theta and   *
+                                * the five-point fourth-order difference along phi; fourth-    *
+                                * order central flux differences for -div(u phi) and grad mu.  *
+                                * mu and the advection fluxes come from a prepass per stage    *
+                                * (the library allocates 3 planes for them); tiles of 8 rows   *
+                                * only, not in batches, not with TLB_WENO5                     */
 
 /* Physical and numerical parameters, in the paper's units (k_B T = m = 1, so the kinematic
  * viscosity is nu = tau, eq. nu).
@@ -81,7 +88,8 @@ extern "C" {
  *   tau         BGK relaxation time (> 0)
  *   dt          time step of the three-stage SSP Runge-Kutta integrator (> 0)
  *   precision   32 or 64: element type T of every device buffer of this grid
- *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT
+ *   flags       TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT |
+ *               TLB_CH4
  *   check_every 0: tlb_step_n does not look at the state.  K > 0: tlb_step_n counts the
  *               non-finite values of the state (f and phi) after every K steps of a call and
  *               after its last step, waits for the stream at its end and returns

@@ -24,6 +24,7 @@ CH_NO_ADVECTION = 2
 NO_GRAPH = 4
 WENO5 = 8
 STRICT_DT = 16
+CH4 = 32
 
 EXPORTED = ("tlb_stable_dt", "tlb_create_torus_grid", "tlb_set_state", "tlb_step_n", "tlb_get_moments",
             "tlb_get_state", "tlb_invariants", "tlb_diagnostics", "tlb_destroy",

@@ -1044,9 +1044,9 @@ void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* p
 // one learned step of grid g: three stage launches, moments, network, correction
 void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) {
   for (int st = 1; st <= 3; ++st) {
-    tlbi_launch l;
-    tlbi_stage_launch(g, st, &l);
-    seq.push_back(l);
+    tlbi_launch l[2];
+    const int n = tlbi_stage_launches(g, st, l);
+    for (int i = 0; i < n; ++i) seq.push_back(l[i]);
   }
   if (g->p.precision == 64)
     pair_launch<double>(g, nullptr, net->mbuf, nullptr, seq);

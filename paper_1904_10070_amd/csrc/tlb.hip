@@ -185,6 +185,11 @@ struct RowCoef {
   T inv_2rJdth;  // 1 / (2 r J_q dtheta)
   T bsum_p;      // sum of bth_p: the theta advection of a theta-independent value (v > 0)
   T bsum_m;      // sum of bth_m (v < 0)
+  // fourth-order Cahn-Hilliard operators (TLB_CH4)
+  T l4[4];        // J at theta_{q-3/2}, _{q-1/2}, _{q+1/2}, _{q+3/2}, over 576 r^2 J_q dtheta^2
+  T lp4;          // 1 / (12 J_q^2 dphi^2)
+  T inv_12Jdph;   // 1 / (12 J_q dphi)
+  T inv_12rJdth;  // 1 / (12 r J_q dtheta)
 };
 
 template <typename T>
@@ -192,6 +197,7 @@ struct Consts {
   T A, kappa, M, inv_tau, inv_2rdth, dt;
   T n_ref;  // reference density of the stored deviations (FP32)
   int ch_adv;
+  T inv_12rdth;  // 1 / (12 r dtheta) (TLB_CH4)
 };
 
 template <typename T>
@@ -208,6 +214,26 @@ struct StageArgs {
   T a0, b1;         // out = a0 * y^n + b1 * (y_s + dt L(y_s))
   int has_y0;       // a0 != 0
   Consts<T> c;
+  const T* mu4;     // TLB_CH4: mu, J u^theta phi, u^phi phi of the stage input (prepass)
+  const T* P4;
+  const T* Q4;
+};
+
+// The fourth-order Cahn-Hilliard prepass (TLB_CH4) of one Runge-Kutta stage: per node of the
+// stage input, the chemical potential with the fourth-order surface Laplacian (eq. mu) and the
+// two Cahn-Hilliard advection fluxes J u^theta phi and u^phi phi; the stage kernel then reads
+// them as halo tiles like the populations.
+template <typename T>
+struct Ch4Args {
+  const T* f;
+  const T* phi;
+  T* mu;
+  T* P;
+  T* Q;
+  const RowCoef<T>* rows;
+  int nt, np;
+  long long plane;
+  T A, kappa, n_ref;
 };
 
 __device__ __forceinline__ int wrapi(int x, int n) {
@@ -445,7 +471,7 @@ struct Ring {
 // density is read from the arguments; otherwise it is the constant 1 (every grid near unit
 // density), whose products the compiler folds away.
 template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false,
-          bool GENREF = false>
+          bool GENREF = false, bool CH4 = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, const int ty) {
 // (the body is device code: the host pass of the single-source compiler skips it; with both
 // advection variants instantiated, that pass otherwise rejects the call from the batch kernel)
@@ -475,6 +501,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     else return sF7;
   };
   __shared__ T sPhi[PY * LXT];
+  // TLB_CH4: mu, J u^theta phi and u^phi phi of the prepass, halo tiles like the populations
+  __shared__ T sMu4[CH4 ? TILE_SLOTS : 1], sP4[CH4 ? TILE_SLOTS : 1], sQ4[CH4 ? TILE_SLOTS : 1];
   __shared__ T sMu[(TY + 2) * (TX + 2)];
   __shared__ T sPt[(TY + 2) * TX];  // J u^theta phi on the tile and the rows above/below
   __shared__ T sPp[TY * (TX + 2)];  // u^phi phi on the tile and the columns left/right
@@ -502,6 +530,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   cp_f.init(lx, wave, q0, s0, nt, np, interior);
   const unsigned plane_bytes = (unsigned)(a.plane * (long long)sizeof(T));
   cp_phi.issue(a.phin, plane_bytes, sPhi, wave);
+  if constexpr (CH4) {  // issued before the populations: the loop's first wait covers them
+    cp_f.issue(a.mu4, plane_bytes, sMu4, wave);
+    cp_f.issue(a.P4, plane_bytes, sP4, wave);
+    cp_f.issue(a.Q4, plane_bytes, sQ4, wave);
+  }
   static_for<0, D>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     cp_f.issue(a.fin + k * a.plane, plane_bytes, slot(ic<k>{}), wave);
@@ -513,7 +546,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   else if (tid < 2 * TX) { ry = TY; rx = tid - TX; }
   else if (tid < 2 * TX + TY) { ry = tid - 2 * TX; rx = -1; }
   else { ry = tid - 2 * TX - TY; rx = TX; }
-  const bool ring = tid < NRING;
+  const bool ring = !CH4 && tid < NRING;  // CH4 takes the ring's fluxes from the prepass
   if (!ring) { ry = 0; rx = 0; }
   const RowCoef<T>& rrc = a.rows[wrapi(q0 + ry, nt)];
 
@@ -643,7 +676,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
 
   // ---- chemical potential on the tile and the ring (the order-parameter tile has landed:
   //      its copy was issued before population 0's)
-  sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
+  if constexpr (!CH4) sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
   if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
 
   // ---- CH fluxes of the tile and the ring
@@ -656,8 +689,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const T inv_n = recip(n);
   const T ut = nut * inv_n, up = nup * inv_n;
   const T phc = sPhi[(ly + 2) * LXT + lx + CX];
-  sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
-  sPp[ly * (TX + 2) + lx + 1] = up * phc;
+  if constexpr (!CH4) {
+    sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
+    sPp[ly * (TX + 2) + lx + 1] = up * phc;
+  }
   if (ring) {
     const T phr = sPhi[(ry + 2) * LXT + rx + CX];
     const T inv_rn = recip(rn);
@@ -667,18 +702,44 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   __syncthreads();
 
   // ---- interface force n F = -phi grad mu and the Cahn-Hilliard right-hand side
-  const int cm = (ly + 1) * (TX + 2) + lx + 1;
-  const T mu_c = sMu[cm], mu_n = sMu[cm + TX + 2], mu_s = sMu[cm - (TX + 2)];
-  const T mu_e = sMu[cm + 1], mu_w = sMu[cm - 1];
-  const T Fth = -phc * (mu_n - mu_s) * a.c.inv_2rdth * inv_n;
-  const T Fph = -phc * (mu_e - mu_w) * rc.inv_2Jdph * inv_n;
-  const T lapmu = rc.lap_n * (mu_n - mu_c) - rc.lap_s * (mu_c - mu_s) +
-                  rc.lap_p * (mu_e - T(2) * mu_c + mu_w);
-  T Lphi = a.c.M * lapmu;
-  if (a.c.ch_adv) {
-    const int ct = (ly + 1) * TX + lx, cp = ly * (TX + 2) + lx + 1;
-    Lphi -= (sPt[ct + TX] - sPt[ct - TX]) * rc.inv_2rJdth +
-            (sPp[cp + 1] - sPp[cp - 1]) * rc.inv_2Jdph;
+  T Fth, Fph, Lphi;
+  if constexpr (CH4) {
+    // fourth-order central grad mu, the fourth-order surface Laplacian of mu (staggered along
+    // theta: face gradients (m_{a-1} - 27 m_a + 27 m_{a+1} - m_{a+2}) at the faces a+1/2,
+    // a = q-2 .. q+1, weighted by J_face / (576 r^2 J dtheta^2) with (1, -27, 27, -1); the
+    // five-point fourth-order difference along phi) and fourth-order central flux differences
+    const T* m = sMu4 + cN;
+    auto G = [&](int o) {  // face gradient numerator at the face (q + o) + 1/2
+      return m[(o - 1) * LXT] - T(27) * m[o * LXT] + T(27) * m[(o + 1) * LXT] - m[(o + 2) * LXT];
+    };
+    const T dmu_th = (m[-2 * LXT] - T(8) * m[-LXT]) + (T(8) * m[LXT] - m[2 * LXT]);
+    const T dmu_ph = (m[-2] - T(8) * m[-1]) + (T(8) * m[1] - m[2]);
+    Fth = -phc * dmu_th * a.c.inv_12rdth * inv_n;
+    Fph = -phc * dmu_ph * rc.inv_12Jdph * inv_n;
+    const T lap_th = rc.l4[0] * G(-2) - T(27) * (rc.l4[1] * G(-1)) + T(27) * (rc.l4[2] * G(0)) -
+                     rc.l4[3] * G(1);
+    const T lap_ph = rc.lp4 * ((-m[-2] + T(16) * m[-1]) - T(30) * m[0] + (T(16) * m[1] - m[2]));
+    Lphi = a.c.M * (lap_th + lap_ph);
+    if (a.c.ch_adv) {
+      const T* P = sP4 + cN;
+      const T* Q = sQ4 + cN;
+      Lphi -= ((P[-2 * LXT] - T(8) * P[-LXT]) + (T(8) * P[LXT] - P[2 * LXT])) * rc.inv_12rJdth +
+              ((Q[-2] - T(8) * Q[-1]) + (T(8) * Q[1] - Q[2])) * rc.inv_12Jdph;
+    }
+  } else {
+    const int cm = (ly + 1) * (TX + 2) + lx + 1;
+    const T mu_c = sMu[cm], mu_n = sMu[cm + TX + 2], mu_s = sMu[cm - (TX + 2)];
+    const T mu_e = sMu[cm + 1], mu_w = sMu[cm - 1];
+    Fth = -phc * (mu_n - mu_s) * a.c.inv_2rdth * inv_n;
+    Fph = -phc * (mu_e - mu_w) * rc.inv_2Jdph * inv_n;
+    const T lapmu = rc.lap_n * (mu_n - mu_c) - rc.lap_s * (mu_c - mu_s) +
+                    rc.lap_p * (mu_e - T(2) * mu_c + mu_w);
+    Lphi = a.c.M * lapmu;
+    if (a.c.ch_adv) {
+      const int ct = (ly + 1) * TX + lx, cp = ly * (TX + 2) + lx + 1;
+      Lphi -= (sPt[ct + TX] - sPt[ct - TX]) * rc.inv_2rJdth +
+              (sPp[cp + 1] - sPp[cp - 1]) * rc.inv_2Jdph;
+    }
   }
 
 
@@ -767,13 +828,56 @@ struct StageWaves {
 };
 
 template <typename T, bool VEC, int TY, bool WENO = false, bool STREAM = false,
-          bool GENREF = false>
+          bool GENREF = false, bool CH4 = false>
 __global__ __launch_bounds__(Tile<TY>::NT) __attribute__((amdgpu_waves_per_eu(
     StageWaves<T>::value))) void tlb_stage_kernel(StageArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, a.ntx * a.nty);
   int tx, ty;
   band_tile(tile, a.ntx, a.nty, tx, ty);
-  stage_tile<T, VEC, TY, WENO, STREAM, GENREF>(a, tx, ty);
+  stage_tile<T, VEC, TY, WENO, STREAM, GENREF, CH4>(a, tx, ty);
+}
+
+// The fourth-order surface Laplacian (TLB_CH4) of a plane h at node (q, s), read from global
+// memory: staggered along theta (face gradient numerators h_{a-1} - 27 h_a + 27 h_{a+1} -
+// h_{a+2} at the faces a+1/2, a = q-2 .. q+1, weighted by rc.l4 with (1, -27, 27, -1)), the
+// five-point fourth-order difference along phi.
+template <typename T>
+__device__ __forceinline__ T lap4_at(const T* h, const RowCoef<T>& rc, int q, int s, int nt,
+                                     int np) {
+  T c[7];  // rows q-3 .. q+3 of column s
+#pragma unroll
+  for (int o = -3; o <= 3; ++o) c[o + 3] = h[(long long)wrapi(q + o, nt) * np + s];
+  auto G = [&](int o) { return c[o + 2] - T(27) * c[o + 3] + T(27) * c[o + 4] - c[o + 5]; };
+  const long long row = (long long)q * np;
+  const T e1 = h[row + wrapi(s + 1, np)], e2 = h[row + wrapi(s + 2, np)];
+  const T w1 = h[row + wrapi(s - 1, np)], w2 = h[row + wrapi(s - 2, np)];
+  const T lap_th = rc.l4[0] * G(-2) - T(27) * (rc.l4[1] * G(-1)) + T(27) * (rc.l4[2] * G(0)) -
+                   rc.l4[3] * G(1);
+  const T lap_ph = rc.lp4 * ((-w2 + T(16) * w1) - T(30) * c[3] + (T(16) * e1 - e2));
+  return lap_th + lap_ph;
+}
+
+// TLB_CH4 prepass, one thread per node (see Ch4Args)
+template <typename T>
+__global__ __launch_bounds__(256) void tlb_ch4_prep_kernel(Ch4Args<T> a) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.plane) return;
+  const int q = (int)(x / a.np), s = (int)(x - (long long)q * a.np);
+  T n = T(0), nut = T(0), nup = T(0);
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const T fk = a.f[k * a.plane + x];
+    n += fk;
+    nut += T(vel(k >> 2)) * fk;
+    nup += T(vel(k & 3)) * fk;
+  });
+  if constexpr (stores_deviation<T>()) n += a.n_ref;
+  const T inv_n = recip(n);
+  const RowCoef<T> rc = a.rows[q];
+  const T ph = a.phi[x];
+  a.mu[x] = a.A * ph * (ph * ph - T(1)) - a.kappa * lap4_at(a.phi, rc, q, s, a.nt, a.np);
+  a.P[x] = rc.J * (nut * inv_n) * ph;
+  a.Q[x] = (nup * inv_n) * ph;
 }
 
 // One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
@@ -864,7 +968,7 @@ __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* p
                                                          T* ut_out, T* up_out, T* phi_out,
                                                          T* mu_out, const RowCoef<T>* rows,
                                                          int nt, int np, T A, T kappa,
-                                                         T n_ref) {
+                                                         T n_ref, int ch4) {
   const long long plane = (long long)nt * np;
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= plane) return;
@@ -883,7 +987,9 @@ __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* p
   if (up_out) up_out[x] = nup / n;
   const T ph = phi[x];
   if (phi_out) phi_out[x] = ph;
-  if (mu_out) {
+  if (mu_out && ch4) {
+    mu_out[x] = A * ph * (ph * ph - T(1)) - kappa * lap4_at(phi, rows[q], q, s, nt, np);
+  } else if (mu_out) {
     const RowCoef<T>& rc = rows[q];
     const int qn = q + 1 == nt ? 0 : q + 1, qs = q == 0 ? nt - 1 : q - 1;
     const int se = s + 1 == np ? 0 : s + 1, sw = s == 0 ? np - 1 : s - 1;
@@ -1117,6 +1223,7 @@ Consts<T> make_consts(const tlb_params& p, double n_ref) {
   c.M = T(p.M);
   c.inv_tau = T(1.0 / p.tau);
   c.inv_2rdth = T(1.0 / (2.0 * p.r * dth));
+  c.inv_12rdth = T(1.0 / (12.0 * p.r * dth));
   c.dt = T(p.dt);
   c.ch_adv = (p.flags & TLB_CH_NO_ADVECTION) ? 0 : 1;
   return c;
@@ -1155,6 +1262,11 @@ void make_rows(const tlb_params& p, RowCoef<T>* rows, double* area) {
     rc.lap_p = T(1.0 / (J * J * dph * dph));
     rc.inv_2Jdph = T(1.0 / (2.0 * J * dph));
     rc.inv_2rJdth = T(1.0 / (2.0 * p.r * J * dth));
+    for (int m = 0; m < 4; ++m)
+      rc.l4[m] = T(Jat(th + (m - 1.5) * dth) / (576.0 * p.r * p.r * J * dth * dth));
+    rc.lp4 = T(1.0 / (12.0 * J * J * dph * dph));
+    rc.inv_12Jdph = T(1.0 / (12.0 * J * dph));
+    rc.inv_12rJdth = T(1.0 / (12.0 * p.r * J * dth));
     area[q] = p.r * J * dth * dph;
     area[nt + q] = Jat(th + 0.5 * dth) * dph;
   }
@@ -1202,6 +1314,12 @@ StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
   a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
   a.c = make_consts<T>(g->p, g->n_ref);
+  if (g->ch4) {
+    const T* w = static_cast<const T*>(g->ch4);
+    a.mu4 = w;
+    a.P4 = w + a.plane;
+    a.Q4 = w + 2 * a.plane;
+  }
   return a;
 }
 
@@ -1245,6 +1363,13 @@ bool streaming(const tlb_grid* g) {
 template <typename T>
 const void* stage_fn(const tlb_grid* g) {
   const bool vec = vec_ok<T>(g->p.n_phi), gen = general_reference<T>(g);
+  if (g->p.flags & TLB_CH4) {  // the fourth-order Cahn-Hilliard variant: 8-row tiles only
+    if (gen)
+      return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, false, false, true, true>)
+                 : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, false, false, true, true>);
+    return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, false, false, false, true>)
+               : reinterpret_cast<const void*>(&tlb_stage_kernel<T, false, DEFAULT_TY, false, false, false, true>);
+  }
   if (g->p.flags & TLB_WENO5) {  // the WENO variant exists for the default tile height only
     if (gen)
       return vec ? reinterpret_cast<const void*>(&tlb_stage_kernel<T, true, DEFAULT_TY, true, false, true>)
@@ -1294,12 +1419,50 @@ int stage_blocks(const tlb_grid* g) {
   return ((g->p.n_phi + TX - 1) / TX) * ((g->p.n_theta + g->ty - 1) / g->ty);
 }
 
+// The launches of Runge-Kutta stage `stage` of grid g, each with one by-value argument block:
+// the stage kernel, preceded for TLB_CH4 by the fourth-order Cahn-Hilliard prepass on the
+// stage input.  Returns their number (1 or 2).
+template <typename T>
+int stage_launches(const tlb_grid* g, int stage, tlbi_launch out[2]) {
+  static_assert(sizeof(StageArgs<T>) <= sizeof(out->args), "argument block");
+  static_assert(sizeof(Ch4Args<T>) <= sizeof(out->args), "argument block");
+  const StageArgs<T> a = stage_args<T>(g, stage);
+  int n = 0;
+  if (g->ch4) {
+    Ch4Args<T> c{};
+    c.f = a.fin;
+    c.phi = a.phin;
+    c.mu = const_cast<T*>(a.mu4);
+    c.P = const_cast<T*>(a.P4);
+    c.Q = const_cast<T*>(a.Q4);
+    c.rows = a.rows;
+    c.nt = a.nt;
+    c.np = a.np;
+    c.plane = a.plane;
+    c.A = T(g->p.A);
+    c.kappa = T(g->p.kappa);
+    c.n_ref = T(g->n_ref);
+    out[n].fn = reinterpret_cast<const void*>(&tlb_ch4_prep_kernel<T>);
+    out[n].grid = dim3((unsigned)((a.plane + 255) / 256));
+    out[n].block = dim3(256);
+    std::memcpy(out[n].args, &c, sizeof(c));
+    ++n;
+  }
+  out[n].fn = stage_fn<T>(g);
+  out[n].grid = dim3(stage_blocks(g));
+  out[n].block = dim3(TX * g->ty);
+  std::memcpy(out[n].args, &a, sizeof(a));
+  return n + 1;
+}
+
 template <typename T>
 int32_t launch_stage(tlb_grid* g, int stage) {
-  StageArgs<T> a = stage_args<T>(g, stage);
-  void* params[] = {&a};
-  TLB_HIP_CHECK(hipLaunchKernel(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(TX * g->ty), params,
-                                0, g->stream));
+  tlbi_launch l[2];
+  const int n = stage_launches<T>(g, stage, l);
+  for (int i = 0; i < n; ++i) {
+    void* params[] = {l[i].args};
+    TLB_HIP_CHECK(hipLaunchKernel(l[i].fn, l[i].grid, l[i].block, params, 0, g->stream));
+  }
   return TLB_OK;
 }
 
@@ -1338,13 +1501,41 @@ hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_pa
   return e;
 }
 
+// A chain of `steps` time steps of the grid's stage launches (kernel nodes only), each node
+// depending on the one before.
 template <typename T>
 int32_t build_step_graph(tlb_grid* g, int steps) {
-  StageArgs<T> args[3] = {stage_args<T>(g, 1), stage_args<T>(g, 2), stage_args<T>(g, 3)};
-  void* params[3][1] = {{&args[0]}, {&args[1]}, {&args[2]}};
-  hipError_t e = build_chain(stage_fn<T>(g), dim3(stage_blocks(g)), dim3(TX * g->ty),
-                             [&](int st) { return params[st - 1]; }, steps, &g->graphs[steps]);
+  tlbi_launch l[3][2];
+  int n[3];
+  void* argp[3][2];
+  for (int st = 1; st <= 3; ++st) {
+    n[st - 1] = stage_launches<T>(g, st, l[st - 1]);
+    for (int i = 0; i < n[st - 1]; ++i) argp[st - 1][i] = l[st - 1][i].args;
+  }
+  hipGraph_t graph;
+  hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
+  hipGraphNode_t prev = nullptr;
+  for (int t = 0; t < steps && e == hipSuccess; ++t)
+    for (int st = 0; st < 3 && e == hipSuccess; ++st)
+      for (int i = 0; i < n[st] && e == hipSuccess; ++i) {
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(l[st][i].fn);
+        kp.gridDim = l[st][i].grid;
+        kp.blockDim = l[st][i].block;
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = &argp[st][i];
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        prev = node;
+      }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->graphs[steps], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g->graphs[steps] = nullptr;
+    return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
+  }
   return TLB_OK;
 }
 
@@ -1605,7 +1796,7 @@ int32_t moments_t(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu)
                      static_cast<T*>(n), static_cast<T*>(ut), static_cast<T*>(up),
                      static_cast<T*>(phi), static_cast<T*>(mu),
                      static_cast<const RowCoef<T>*>(g->rows), g->p.n_theta, g->p.n_phi,
-                     T(g->p.A), T(g->p.kappa), T(g->n_ref));
+                     T(g->p.A), T(g->p.kappa), T(g->n_ref), (g->p.flags & TLB_CH4) ? 1 : 0);
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
@@ -1683,8 +1874,11 @@ int32_t check_params(const tlb_params* p) {
   if (!std::isfinite(p->A)) return fail(TLB_EINVAL, "A must be finite");
   if (p->precision != 32 && p->precision != 64)
     return fail(TLB_EINVAL, "precision must be 32 or 64");
-  if (p->flags & ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT))
+  if (p->flags &
+      ~(TLB_FLAT | TLB_CH_NO_ADVECTION | TLB_NO_GRAPH | TLB_WENO5 | TLB_STRICT_DT | TLB_CH4))
     return fail(TLB_EINVAL, "unknown flag");
+  if ((p->flags & TLB_CH4) && (p->flags & TLB_WENO5))
+    return fail(TLB_EINVAL, "TLB_CH4 and TLB_WENO5 cannot be combined");
   if (p->check_every < 0) return fail(TLB_EINVAL, "check_every must be >= 0");
   return TLB_OK;
 }
@@ -1709,20 +1903,9 @@ std::atomic<unsigned long long> g_next_uid{1};
 // ------------------------------------------------------------------------------------------
 int32_t tlbi_fail(int32_t code, const std::string& msg) { return fail(code, msg); }
 
-void tlbi_stage_launch(const tlb_grid* g, int stage, tlbi_launch* out) {
-  out->grid = dim3(stage_blocks(g));
-  out->block = dim3(TX * g->ty);
-  if (g->p.precision == 64) {
-    static_assert(sizeof(StageArgs<double>) <= sizeof(out->args), "argument block");
-    out->fn = stage_fn<double>(g);
-    StageArgs<double> a = stage_args<double>(g, stage);
-    std::memcpy(out->args, &a, sizeof(a));
-  } else {
-    static_assert(sizeof(StageArgs<float>) <= sizeof(out->args), "argument block");
-    out->fn = stage_fn<float>(g);
-    StageArgs<float> a = stage_args<float>(g, stage);
-    std::memcpy(out->args, &a, sizeof(a));
-  }
+int tlbi_stage_launches(const tlb_grid* g, int stage, tlbi_launch out[2]) {
+  return g->p.precision == 64 ? stage_launches<double>(g, stage, out)
+                              : stage_launches<float>(g, stage, out);
 }
 
 namespace {
@@ -1961,6 +2144,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
     if (g->half_len) (void)hipFree(g->half_len);
     if (g->check_flag) (void)hipFree(g->check_flag);
     if (g->proj) (void)hipFree(g->proj);
+    if (g->ch4) (void)hipFree(g->ch4);
     delete g;
     return fail(code, msg);
   };
@@ -1978,6 +2162,8 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->half_len), sizeof(double) * nt);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->check_flag), sizeof(int));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->proj), sizeof(double) * 3 * nt);
+  if (e == hipSuccess && (params->flags & TLB_CH4))
+    e = hipMalloc(&g->ch4, 3 * (size_t)nt * params->n_phi * g->elem);
   if (e != hipSuccess)
     return cleanup(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipMemcpyAsync(g->rows, host_rows, row_bytes * nt, hipMemcpyHostToDevice, g->stream);
@@ -2006,6 +2192,7 @@ void tlb_destroy(tlb_grid* g) {
   (void)hipFree(g->half_len);
   (void)hipFree(g->check_flag);
   (void)hipFree(g->proj);
+  if (g->ch4) (void)hipFree(g->ch4);
   delete g;
 }
 
@@ -2119,8 +2306,8 @@ int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
   clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
   if (rows != 4 && rows != 8 && rows != 16) return fail(TLB_EINVAL, "tile rows must be 4, 8 or 16");
-  if ((g->p.flags & TLB_WENO5) && rows != DEFAULT_TY)
-    return fail(TLB_EINVAL, "the WENO-5 variant runs with tiles of 8 rows only");
+  if ((g->p.flags & (TLB_WENO5 | TLB_CH4)) && rows != DEFAULT_TY)
+    return fail(TLB_EINVAL, "the WENO-5 and fourth-order CH variants run with tiles of 8 rows only");
   if (g->ty != rows) {
     g->ty = rows;
     drop_graph(g);
@@ -2131,7 +2318,7 @@ int32_t tlb_set_tile_rows(tlb_grid* g, int32_t rows) {
 int32_t tlb_autotune(tlb_grid* g, int32_t* rows) {
   clear_error();
   if (!g) return fail(TLB_EINVAL, "grid is NULL");
-  if (g->p.flags & TLB_WENO5) {  // one tile height only
+  if (g->p.flags & (TLB_WENO5 | TLB_CH4)) {  // one tile height only
     if (rows) *rows = g->ty;
     return TLB_OK;
   }
@@ -2149,8 +2336,8 @@ int32_t tlb_create_batch(tlb_grid* const* grids, int32_t n, void* hip_stream, tl
       return fail(TLB_EINVAL, "all grids of a batch must have the same precision");
     for (int j = 0; j < i; ++j)
       if (grids[j] == grids[i]) return fail(TLB_EINVAL, "a grid appears twice in the batch");
-    if (grids[i]->p.flags & TLB_WENO5)
-      return fail(TLB_EINVAL, "the WENO-5 variant is not available in batches");
+    if (grids[i]->p.flags & (TLB_WENO5 | TLB_CH4))
+      return fail(TLB_EINVAL, "the WENO-5 and fourth-order CH variants are not available in batches");
   }
   tlb_batch* b = new (std::nothrow) tlb_batch{};
   if (!b) return fail(TLB_ENOMEM, "host allocation failed");

@@ -37,6 +37,7 @@ struct tlb_grid {
   unsigned long long uid;  // unique over the process: graphs kept elsewhere key on it
   int* check_flag;   // [1]: set by the non-finite check of tlb_step_n (check_every > 0)
   double* proj;      // [3 nt]: per-row sums of the learned correction (tlb_apply_correction)
+  void* ch4;         // TLB_CH4: mu, J u^theta phi, u^phi phi of a stage input (3 planes of T)
 };
 
 // Records `msg` as the thread's last error and returns `code`.
@@ -49,8 +50,9 @@ struct tlbi_launch {
   alignas(16) unsigned char args[512];
 };
 
-// The launch of Runge-Kutta stage `stage` (1..3) of one time step of grid g.
-void tlbi_stage_launch(const tlb_grid* g, int stage, tlbi_launch* out);
+// The launches of Runge-Kutta stage `stage` (1..3) of one time step of grid g (the stage
+// kernel, preceded by a prepass for TLB_CH4); returns their number (1 or 2).
+int tlbi_stage_launches(const tlb_grid* g, int stage, tlbi_launch out[2]);
 
 namespace {
 

@@ -58,18 +58,30 @@ def run_ensemble(starts, precision, t_end, every_t=1.0, progress=None):
         g.set_state(inputs.stripe_phi(p, th0, w0), *inputs.rest_moments(p.n_theta, p.n_phi))
         grids.append(g)
     m0 = [g.invariants()[0] for g in grids]
-    batch = TorusBatch(grids)
-    t, recs = stripe.record(batch.step, grids, t_end, every_t,
+    if any(p.flags & CH4 for p, _, _ in starts):  # no batches for the fourth-order variant
+        batch = None
+
+        def step(k):
+            for g in grids:
+                g.step(k)
+    else:
+        batch = TorusBatch(grids)
+        step = batch.step
+    t, recs = stripe.record(step, grids, t_end, every_t,
                             lambda g: stripe.stripe_state(g, band_sign=-1.0), progress)
     drift = [abs(g.invariants()[0] - m) / m for g, m in zip(grids, m0)]
-    batch.close()
+    if batch is not None:
+        batch.close()
     for g in grids:
         g.close()
     return t, [np.array(r) for r in recs], drift
 
 
-def fork(precision=64, t_end=3000.0, progress=None, n_theta=320):
-    p = inputs.TorusParams(**dict(BASE, n_theta=n_theta))
+CH4 = 32  # the fourth-order Cahn-Hilliard variant (include/tlb.h)
+
+
+def fork(precision=64, t_end=3000.0, progress=None, n_theta=320, flags=0):
+    p = inputs.TorusParams(**dict(BASE, n_theta=n_theta), flags=flags)
     starts = [(p, 0.5 * math.pi, w * math.pi) for w in FORK_WIDTHS]
     t, recs, drift = run_ensemble(starts, precision, t_end, progress=progress)
     rows = []
@@ -124,8 +136,10 @@ def main(argv):
     if what == "fork":
         t_end = float(argv[3]) if len(argv) > 3 else 3000.0
         n_theta = int(argv[4]) if len(argv) > 4 else 320
-        t, rows = fork(prec, t_end, prog, n_theta)
-        print(f"FP{prec}, N_theta = {n_theta}, t_end = {t_end:g}")
+        flags = CH4 if len(argv) > 5 and argv[5] == "ch4" else 0
+        t, rows = fork(prec, t_end, prog, n_theta, flags)
+        print(f"FP{prec}, N_theta = {n_theta}, t_end = {t_end:g}, "
+              f"Cahn-Hilliard order {4 if flags else 2}")
         print("| width_0 | dA / dA_crit | paper | here | crossings of pi | last crossing | "
               "theta_c end | theta_eq | width end | width_eq |")
         print("|" + "---|" * 10)

@@ -34,19 +34,22 @@ N_PHI = 64
 DT = 5e-4
 
 
-def torus(r, n_theta, nu, kappa=5e-4, M=None, dt=DT):
+CH4 = 32  # the fourth-order Cahn-Hilliard variant (include/tlb.h)
+
+
+def torus(r, n_theta, nu, kappa=5e-4, M=None, dt=DT, flags=0):
     """A torus of the sweep: R = r / 0.4, A = 0.5, M = nu unless given."""
     return inputs.TorusParams(r, r / 0.4, n_theta, N_PHI, 0.5, kappa, nu if M is None else M,
-                              nu, dt)
+                              nu, dt, flags)
 
 
-def configs(geometries=GEOMETRIES, cases=tuple(CASES), nus=NU_SET, kappas=KAPPA_SET):
+def configs(geometries=GEOMETRIES, cases=tuple(CASES), nus=NU_SET, kappas=KAPPA_SET, flags=0):
     """(case, TorusParams) of the sweep."""
     out = []
     for r, nt in geometries:
         for case in cases:
             for nu, kappa in [(nu, 5e-4) for nu in nus] + [(2.5e-3, k) for k in kappas]:
-                out.append((case, torus(r, nt, nu, kappa)))
+                out.append((case, torus(r, nt, nu, kappa, flags=flags)))
     return out
 
 
@@ -61,16 +64,26 @@ def run(cfgs, precision, t_end, every_t=1.0, progress=None):
                     *inputs.rest_moments(p.n_theta, p.n_phi))
         grids.append(g)
     m0 = [g.invariants()[0] for g in grids]
-    batch = TorusBatch(grids)
-    t, recs = stripe.record(batch.step, grids, t_end, every_t,
+    if any(p.flags & CH4 for _, p in cfgs):  # no batches for the fourth-order variant
+        batch = None
+
+        def step(k):
+            for g in grids:
+                g.step(k)
+    else:
+        batch = TorusBatch(grids)
+        step = batch.step
+    t, recs = stripe.record(step, grids, t_end, every_t,
                             lambda g: stripe.stripe_state(g, band_sign=-1.0), progress)
     out = []
     for (case, p), g, rec, m in zip(cfgs, grids, recs, m0):
         rec = np.array(rec)
         res = analyse(case, p, t, rec[:, 0], rec[:, 1])
         res["mass_drift"] = abs(g.invariants()[0] - m) / m
+        res["flags"] = p.flags
         out.append(res)
-    batch.close()
+    if batch is not None:
+        batch.close()
     for g in grids:
         g.close()
     return out
@@ -92,12 +105,13 @@ def analyse(case, p, t, centre, width):
 
 
 def table(rows):
-    head = ("| case | r | N_theta | nu | M | kappa | omega_0 | omega fit | alpha_nu | alpha fit | "
-            "omega / alpha (phase, offset free) | theta_c end - eq |")
-    lines = [head, "|" + "---|" * 12]
+    head = ("| case | CH order | r | N_theta | nu | M | kappa | omega_0 | omega fit | alpha_nu | "
+            "alpha fit | omega / alpha (phase, offset free) | theta_c end - eq |")
+    lines = [head, "|" + "---|" * 13]
     for x in rows:
         lines.append(
-            f"| {x['case']} | {x['r']} | {x['n_theta']} | {x['nu']:.2e} | {x['M']:.2e} | "
+            f"| {x['case']} | {4 if x.get('flags', 0) & CH4 else 2} | {x['r']} | {x['n_theta']} | "
+            f"{x['nu']:.2e} | {x['M']:.2e} | "
             f"{x['kappa']:.2e} | {x['omega0']:.5f} | "
             f"{x['omega_fit']:.5f} ({x['omega_fit'] / x['omega0'] - 1:+.1%}) | "
             f"{x['alpha_nu']:.2e} | {x['alpha_fit']:.2e} ({x['alpha_fit'] / x['alpha_nu']:.2f}x) | "
@@ -109,8 +123,14 @@ def table(rows):
 def main(argv):
     prec = int(argv[1]) if len(argv) > 1 else 64
     t_end = float(argv[2]) if len(argv) > 2 else 800.0
-    rows = run(configs(), prec, t_end,
-               progress=lambda t: print(f"  t = {t:.0f}", flush=True))
+    if len(argv) > 3 and argv[3] == "ch4":
+        # the second- against the fourth-order Cahn-Hilliard discretisation on the r = 0.8,
+        # N_theta = 320 torus (nu sweep at kappa = 5e-4)
+        cfgs = [(c, p.with_(flags=fl)) for fl in (0, CH4)
+                for c, p in configs(geometries=((0.8, 320),), kappas=())]
+    else:
+        cfgs = configs()
+    rows = run(cfgs, prec, t_end, progress=lambda t: print(f"  t = {t:.0f}", flush=True))
     print(f"FP{prec}, t_end = {t_end:g}")
     print(table(rows))
     print("largest mass drift", max(x["mass_drift"] for x in rows))

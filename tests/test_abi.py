@@ -48,7 +48,8 @@ def params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(r=0.0), dict(R=1.0), dict(n_theta=0), dict(n_phi=-3),
                                  dict(dt=0.0), dict(tau=0.0), dict(kappa=-1.0), dict(M=-0.1),
-                                 dict(precision=16), dict(flags=32), dict(A=float("nan")),
+                                 dict(precision=16), dict(flags=64), dict(A=float("nan")),
+                                 dict(flags=32 | 8),
                                  dict(n_theta=100000, n_phi=100000, precision=64),
                                  dict(check_every=-1)])
 def test_create_rejects_bad_parameters(lib, bad):
@@ -99,7 +100,7 @@ def test_null_handles_rejected(lib):
 
 def test_weno_flag_is_accepted_by_validation(lib):
     """Flag 8 passes parameter validation (the create call then fails only for want of a GPU
-    or succeeds on one); 32 does not."""
+    or succeeds on one); 64 does not."""
     p = params(flags=8)
     b = binding.Buffers()
     for i in range(3):

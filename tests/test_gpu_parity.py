@@ -295,3 +295,57 @@ def test_uneven_mixture_full_size_fp64_and_fp32(torch_cuda):
     e32f, e32p = rel_linf(f32, f_ref), rel_linf(p32, phi_ref)
     print(f"512x1280 mean -0.3 fp32 after 2 steps: f {e32f:.2e} phi {e32p:.2e}", flush=True)
     assert e32f <= 1e-5 and e32p <= 1e-5
+
+
+@pytest.mark.parametrize("shape,flags", [((64, 160), 32), ((37, 150), 32), ((9, 70), 32 | 1),
+                                         ((24, 96), 32 | 2), ((6, 1), 32), ((4, 64), 32 | 4)])
+def test_ch4_variant_fp64(torch_cuda, shape, flags):
+    """The fourth-order Cahn-Hilliard variant (flag 32: prepass of mu and the advection
+    fluxes, fourth-order operators in the stage kernel) against the oracle's, alone and with
+    the flat, no-CH-advection and no-graph flags, on a drop and on random states (ragged tiles,
+    grids narrower than the stencils)."""
+    nt, np_ = shape
+    if shape == (64, 160):
+        p = inputs.drop_workload().with_(flags=flags)
+        phi = inputs.drop_workload_phi(p, seed=1)
+        n, ut, up = inputs.rest_moments(nt, np_)
+        steps = 400
+    else:
+        p = inputs.TorusParams(1.0, 2.5, nt, np_, 0.5, 2e-3, 0.05, 0.3, 2e-4, flags)
+        phi, n, ut, up = inputs.random_state(p, seed=nt + 3 * np_)
+        steps = 40
+    compare_fp64(p, phi, n, ut, up, steps, flags_note=f"CH4 flags={flags}")
+
+
+def test_ch4_variant_fp32_tolerance(torch_cuda):
+    """The drop workload with the fourth-order variant in FP32 against the FP64 oracle after
+    2000 steps, within the FP32 bars of the second-order scheme."""
+    p = inputs.drop_workload().with_(flags=32)
+    phi = inputs.drop_workload_phi(p, seed=1)
+    n, ut, up = inputs.rest_moments(p.n_theta, p.n_phi)
+    og, f_ref, phi_ref = oracle_run(p, phi, n, ut, up, 2000)
+    gg, f_gpu, phi_gpu = gpu_run(p, phi, n, ut, up, 2000, precision=32)
+    ef, ep = rel_linf(f_gpu, f_ref), rel_linf(phi_gpu, phi_ref)
+    mr, mg = og.moments(), moments_np(gg.moments())
+    en = rel_linf(mg["n"], mr["n"])
+    print(f"CH4 fp32 vs fp64 oracle: f {ef:.2e} phi {ep:.2e} n {en:.2e}", flush=True)
+    assert ef <= 1.5e-3 and ep <= 1e-3 and en <= 1.5e-3
+
+
+def test_ch4_graph_replay_matches_plain_launches_bitwise(torch_cuda):
+    """Two kernels per stage in the replayed graphs (prepass and stage kernel): graph replays
+    and plain launches give the same bits over several calls."""
+    from paper_1904_10070_amd import TorusGrid, NO_GRAPH
+    p = inputs.TorusParams(1.0, 2.5, 40, 96, 0.5, 2e-3, 0.05, 0.3, 2e-4, 32)
+    phi, n, ut, up = inputs.random_state(p, seed=27)
+    a = TorusGrid(p, precision=64)
+    b = TorusGrid(p.with_(flags=32 | NO_GRAPH), precision=64)
+    for g in (a, b):
+        g.set_state(phi, n, ut, up)
+    for call in range(3):
+        a.step(40 + call)
+        b.step(40 + call)
+        torch_cuda.cuda.synchronize()
+        fa, pa = a.get_state()
+        fb, pb = b.get_state()
+        assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb), call
