@@ -52,9 +52,13 @@ def run_ensemble(starts, precision, t_end, every_t=1.0, progress=None):
     """starts: list of (TorusParams, theta_0, width_0).  Returns t and, per stripe, the rows
     (theta_c, width, dp) of every record, and the relative mass drifts."""
     from paper_1904_10070_amd import TorusGrid, TorusBatch, stripe
+    import torch
+    # grids stepped one by one (no batch) each get a stream of their own, so that the small
+    # grids' kernels run side by side
+    own_streams = any(p.flags & CH4 for p, _, _ in starts)
     grids = []
     for p, th0, w0 in starts:
-        g = TorusGrid(p, precision)
+        g = TorusGrid(p, precision, stream=torch.cuda.Stream() if own_streams else None)
         g.set_state(inputs.stripe_phi(p, th0, w0), *inputs.rest_moments(p.n_theta, p.n_phi))
         grids.append(g)
     m0 = [g.invariants()[0] for g in grids]
