@@ -22,15 +22,25 @@
  * far less of the small per-step increments (it otherwise biases the mass by about 1e-2 over
  * 1e6 steps).  tlb_set_state and tlb_get_state convert; a caller reading an FP32 grid's f
  * buffers directly sees deviations.  Precision 64 stores f_k itself.
+ * Precision 32 stores the order parameter as a base plane (owned by the library) plus the
+ * phi buffers, which hold deviations from it: the per-step increments of phi in the bulk,
+ * where phi sits near +-1, are far below half an ulp of 1 and would be rounded away on phi
+ * itself (biasing the sum of phi), while on the small deviations they keep their precision.
+ * After every 32nd time step counted from the last tlb_set_state (or tlb_restrict into the
+ * grid; every learned step also ends with one) the deviation is moved into the base exactly
+ * (error-free two-sum), so a state's bits do not depend on how its steps were split into
+ * calls or checked runs.  tlb_set_state, tlb_get_state, tlb_get_moments and the diagnostics convert; a
+ * caller reading an FP32 grid's phi buffers directly sees deviations.
  * Arithmetic in precision 32 differs from precision 64 in two places beyond the element type:
- * 1/n is the hardware reciprocal (1 ulp), and the Runge-Kutta combination of phi is taken as
- * phi^n + b (phi_s - phi^n + dt L) rather than (1 - b) phi^n + b (phi_s + dt L) (the same
- * value; it avoids a rounding bias of the sum of phi where phi is near +-1).  Grids whose three
- * state copies exceed 1 GiB write their stage outputs with streaming (nontemporal) stores.
+ * 1/n is the hardware reciprocal (1 ulp), and the Runge-Kutta combination of phi is taken on
+ * the deviations as d^n + b (d_s - d^n + dt L) rather than (1 - b) phi^n + b (phi_s + dt L)
+ * (the same value).  Grids whose three state copies exceed 1 GiB write their stage outputs
+ * with streaming (nontemporal) stores.
  *
  * Ownership.  The caller allocates and owns every buffer passed in (state buffers, moment
- * buffers); they must outlive the grid handle.  The library owns only its per-row geometry
- * table, a small reduction workspace and the step graph, all freed by tlb_destroy.
+ * buffers); they must outlive the grid handle.  The library owns its per-row geometry table,
+ * small reduction workspaces, the step graphs, and (precision 32) the order parameter's base
+ * plane and (TLB_CH4) three prepass planes, all freed by tlb_destroy.
  *
  * Streams.  All work is enqueued on the HIP stream given at creation (NULL = the default
  * stream), in call order, asynchronously with respect to the host.  The calls that return

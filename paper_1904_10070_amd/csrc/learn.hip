@@ -548,12 +548,21 @@ __global__ __launch_bounds__(256) void frag_kernel(FragArgs a) {
 // ------------------------------------------------------------------------------------------
 // torus grid <-> network
 
+// A grid's order parameter: FP32 grids store it as base + deviation (phi plane = deviation),
+// FP64 grids whole (base NULL).
+template <typename T>
+__device__ __forceinline__ double order_parameter(const T* phi, const T* base, long long x) {
+  return base ? (double)phi[x] + (double)base[x] : (double)phi[x];
+}
+
 template <typename T>
 struct MomArgs {
   const T* f;
   const T* phi;
+  const T* phib;   // base of phi (FP32) or NULL
   const T* f2;     // truth grid (NULL: moments only)
   const T* phi2;
+  const T* phib2;
   float* m;        // [HW][4]
   float* y;        // [HW][4]
   long long plane;
@@ -561,8 +570,9 @@ struct MomArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ void node_moments(const T* f, const T* phi, long long plane,
-                                             long long x, double n_add, double out[4]) {
+__device__ __forceinline__ void node_moments(const T* f, const T* phi, const T* phib,
+                                             long long plane, long long x, double n_add,
+                                             double out[4]) {
   double n = 0.0, nut = 0.0, nup = 0.0;
   static_for<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -572,7 +582,7 @@ __device__ __forceinline__ void node_moments(const T* f, const T* phi, long long
     nup += vel(k & 3) * fk;
   });
   n += n_add;  // FP32 grids store f - n_ref w_i w_j
-  out[0] = (double)phi[x];
+  out[0] = order_parameter(phi, phib, x);
   out[1] = n;
   out[2] = nut / n;
   out[3] = nup / n;
@@ -583,11 +593,11 @@ __global__ __launch_bounds__(256) void moments_pair_kernel(MomArgs<T> a) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.plane) return;
   double m[4];
-  node_moments(a.f, a.phi, a.plane, x, a.n_add, m);
+  node_moments(a.f, a.phi, a.phib, a.plane, x, a.n_add, m);
   reinterpret_cast<float4*>(a.m)[x] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
   if (a.f2) {
     double t[4];
-    node_moments(a.f2, a.phi2, a.plane, x, a.n_add2, t);
+    node_moments(a.f2, a.phi2, a.phib2, a.plane, x, a.n_add2, t);
     reinterpret_cast<float4*>(a.y)[x] = make_float4((float)(t[0] - m[0]), (float)(t[1] - m[1]),
                                                     (float)(t[2] - m[2]), (float)(t[3] - m[3]));
   }
@@ -692,8 +702,10 @@ template <typename T>
 struct RestrictArgs {
   const T* f;
   const T* phi;
+  const T* phib;  // fine base of phi (FP32) or NULL
   T* fc;
   T* phic;
+  T* phibc;       // coarse base of phi (FP32: the restriction goes there, phic becomes 0)
   const double* area;  // fine rows, proportional to J
   int Hf, Wf, Hc, Wc, k;
   long long plane_f, plane_c;
@@ -718,18 +730,24 @@ __global__ __launch_bounds__(256) void restrict_kernel(RestrictArgs<T> a) {
   den *= (double)a.k;  // the phi weights sum to k
   for (int fld = 0; fld < 17; ++fld) {
     const T* src = fld < 16 ? a.f + fld * a.plane_f : a.phi;
+    const T* base = fld < 16 ? nullptr : a.phib;
     double acc = 0.0;
     for (int d = 0; d <= 2 * h; ++d) {
-      const T* row = src + (size_t)rq[d] * a.Wf;
+      const long long row = (long long)rq[d] * a.Wf;
       double racc = 0.0;
       for (int e = -h; e <= h; ++e) {
         const double w = (e == -h || e == h) ? 0.5 : 1.0;
-        racc += w * (double)row[wrap(a.k * S + e, a.Wf)];
+        racc += w * order_parameter(src, base, row + wrap(a.k * S + e, a.Wf));
       }
       acc += rw[d] * racc;
     }
-    T* dst = fld < 16 ? a.fc + fld * a.plane_c : a.phic;
-    dst[x] = T(acc / den);
+    if (fld == 16 && a.phibc) {
+      a.phibc[x] = T(acc / den);
+      a.phic[x] = T(0);
+    } else {
+      T* dst = fld < 16 ? a.fc + fld * a.plane_c : a.phic;
+      dst[x] = T(acc / den);
+    }
   }
 }
 
@@ -1006,8 +1024,10 @@ void pair_launch(const tlb_grid* g, const tlb_grid* truth, float* m, float* y,
   MomArgs<T> a{};
   a.f = static_cast<const T*>(g->f[0]);
   a.phi = static_cast<const T*>(g->phi[0]);
+  a.phib = reinterpret_cast<const T*>(g->phi_base);
   a.f2 = truth ? static_cast<const T*>(truth->f[0]) : nullptr;
   a.phi2 = truth ? static_cast<const T*>(truth->phi[0]) : nullptr;
+  a.phib2 = truth ? reinterpret_cast<const T*>(truth->phi_base) : nullptr;
   a.m = m;
   a.y = y;
   a.plane = (long long)g->p.n_theta * g->p.n_phi;
@@ -1048,6 +1068,8 @@ void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) 
     const int n = tlbi_stage_launches(g, st, l);
     for (int i = 0; i < n; ++i) seq.push_back(l[i]);
   }
+  tlbi_launch rb;  // FP32: the order parameter's rebase after the step, as tlb_step_n does
+  if (tlbi_phi_rebase_launch(g, &rb)) seq.push_back(rb);
   if (g->p.precision == 64)
     pair_launch<double>(g, nullptr, net->mbuf, nullptr, seq);
   else
@@ -1368,8 +1390,10 @@ int32_t tlb_restrict(const tlb_grid* fine, tlb_grid* coarse) {
     RestrictArgs<T> a{};
     a.f = static_cast<const T*>(fine->f[0]);
     a.phi = static_cast<const T*>(fine->phi[0]);
+    a.phib = reinterpret_cast<const T*>(fine->phi_base);
     a.fc = static_cast<T*>(coarse->f[0]);
     a.phic = static_cast<T*>(coarse->phi[0]);
+    a.phibc = reinterpret_cast<T*>(coarse->phi_base);
     a.area = fine->area;
     a.Hf = pf.n_theta;
     a.Wf = pf.n_phi;
@@ -1388,6 +1412,7 @@ int32_t tlb_restrict(const tlb_grid* fine, tlb_grid* coarse) {
     coarse->n_ref = fine->n_ref;
     ++coarse->version;
   }
+  coarse->phase = 0;  // the coarse order parameter is all base now, as after set_state
   return run_all(seq, coarse->stream);
 }
 
@@ -1450,6 +1475,7 @@ int32_t tlb_learned_step_n(tlb_grid* grid, tlb_cnn* net, int64_t n_steps) {
       if (rc != TLB_OK) return rc;
     }
   }
+  if (n_steps > 0) grid->phase = 0;  // every learned step rebases the order parameter
   return TLB_OK;
 }
 

@@ -214,6 +214,7 @@ struct StageArgs {
   T a0, b1;         // out = a0 * y^n + b1 * (y_s + dt L(y_s))
   int has_y0;       // a0 != 0
   Consts<T> c;
+  const T* phib;    // FP32: the base of the order parameter (phin, phi0, phiout hold deviations)
   const T* mu4;     // TLB_CH4: mu, J u^theta phi, u^phi phi of the stage input (prepass)
   const T* P4;
   const T* Q4;
@@ -227,6 +228,7 @@ template <typename T>
 struct Ch4Args {
   const T* f;
   const T* phi;
+  const T* phib;  // base of the order parameter (FP32) or NULL
   T* mu;
   T* P;
   T* Q;
@@ -244,6 +246,17 @@ __device__ __forceinline__ int wrapi(int x, int n) {
   if (x >= n && x < 2 * n) return x - n;
   int m = x % n;
   return m < 0 ? m + n : m;
+}
+
+// The order parameter at index i: FP32 grids store it as base + deviation (the deviation plane
+// d, the base plane b); FP64 grids store it whole (b = NULL).
+template <typename T>
+__device__ __forceinline__ T phi_val(const T* d, const T* b, long long i) {
+  return b ? d[i] + b[i] : d[i];
+}
+template <typename T>
+__device__ __forceinline__ double phi_val64(const T* d, const T* b, long long i) {
+  return b ? (double)d[i] + (double)b[i] : (double)d[i];
 }
 
 // Block -> tile mapping: consecutive hardware blocks go round-robin over the 8 XCDs; give
@@ -501,6 +514,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     else return sF7;
   };
   __shared__ T sPhi[PY * LXT];
+  __shared__ T sPhiB[stores_deviation<T>() ? PY * LXT : 1];  // FP32: base tile, then phi itself
   // TLB_CH4: mu, J u^theta phi and u^phi phi of the prepass, halo tiles like the populations
   __shared__ T sMu4[CH4 ? TILE_SLOTS : 1], sP4[CH4 ? TILE_SLOTS : 1], sQ4[CH4 ? TILE_SLOTS : 1];
   __shared__ T sMu[(TY + 2) * (TX + 2)];
@@ -530,6 +544,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   cp_f.init(lx, wave, q0, s0, nt, np, interior);
   const unsigned plane_bytes = (unsigned)(a.plane * (long long)sizeof(T));
   cp_phi.issue(a.phin, plane_bytes, sPhi, wave);
+  if constexpr (stores_deviation<T>()) cp_phi.issue(a.phib, plane_bytes, sPhiB, wave);
   if constexpr (CH4) {  // issued before the populations: the loop's first wait covers them
     cp_f.issue(a.mu4, plane_bytes, sMu4, wave);
     cp_f.issue(a.P4, plane_bytes, sP4, wave);
@@ -674,10 +689,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
     pin_reg(rup);
   });
 
+  // ---- FP32: the order-parameter tiles hold the stage input's deviation (sPhi) and the base
+  //      (sPhiB); their sum, the order parameter itself, replaces the base tile.  dsn is the
+  //      node's own deviation, which the Runge-Kutta combine updates.
+  const T* sPhiF = sPhi;
+  T dsn = T(0);
+  if constexpr (stores_deviation<T>()) {
+    dsn = sPhi[(ly + 2) * LXT + lx + CX];
+    for (int i = tid; i < PY * LXT; i += NT) sPhiB[i] += sPhi[i];
+    __syncthreads();
+    sPhiF = sPhiB;
+  }
+
   // ---- chemical potential on the tile and the ring (the order-parameter tile has landed:
   //      its copy was issued before population 0's)
-  if constexpr (!CH4) sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhi, ly, lx, rc, a.c.A, a.c.kappa);
-  if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhi, ry, rx, rrc, a.c.A, a.c.kappa);
+  if constexpr (!CH4) sMu[(ly + 1) * (TX + 2) + lx + 1] = mu_at(sPhiF, ly, lx, rc, a.c.A, a.c.kappa);
+  if (ring) sMu[(ry + 1) * (TX + 2) + rx + 1] = mu_at(sPhiF, ry, rx, rrc, a.c.A, a.c.kappa);
 
   // ---- CH fluxes of the tile and the ring
   // with deviation storage the sums above are n - n_ref; dn keeps that small difference
@@ -688,13 +715,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   }
   const T inv_n = recip(n);
   const T ut = nut * inv_n, up = nup * inv_n;
-  const T phc = sPhi[(ly + 2) * LXT + lx + CX];
+  const T phc = sPhiF[(ly + 2) * LXT + lx + CX];
   if constexpr (!CH4) {
     sPt[(ly + 1) * TX + lx] = rc.J * ut * phc;
     sPp[ly * (TX + 2) + lx + 1] = up * phc;
   }
   if (ring) {
-    const T phr = sPhi[(ry + 2) * LXT + rx + CX];
+    const T phr = sPhiF[(ry + 2) * LXT + rx + CX];
     const T inv_rn = recip(rn);
     if (ry < 0 || ry >= TY) sPt[(ry + 1) * TX + rx] = rrc.J * (rut * inv_rn) * phr;
     else sPp[ry * (TX + 2) + rx + 1] = (rup * inv_rn) * phr;
@@ -746,17 +773,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const int tx, 
   const T dt = a.c.dt, a0 = a.a0, b1 = a.b1;
   const bool y0 = a.has_y0;
   if (active) {
-    const T ys = phc + dt * Lphi;
+    // the stored value at the node: FP32 the deviation from the base, FP64 phi itself
+    const T own = stores_deviation<T>() ? dsn : phc;
+    const T ys = own + dt * Lphi;
     T yn0 = phin;
     if constexpr (!PF)
       if (y0) yn0 = *at_node(a.phi0, row0, lane_bytes);
     T out = ys;
     if constexpr (stores_deviation<T>()) {
-      // FP32: a0 phi^n + b1 (phi_s + dt L) as phi^n + b1 ((phi_s - phi^n) + dt L) (a0 + b1 = 1).
-      // phi is near +-1 in the bulk, where the products a0 phi^n and b1 phi_s round the same
-      // way at every node and bias the sum of phi (by 2e-2 per unit area over 6e6 steps); the
-      // difference of the two nearby values is exact, and the new value is rounded once
-      if (y0) out = yn0 + b1 * ((phc - yn0) + dt * Lphi);
+      // FP32: a0 d^n + b1 (d_s + dt L) as d^n + b1 ((d_s - d^n) + dt L) (a0 + b1 = 1), on the
+      // deviations from the base, which are small where phi sits near +-1 in the bulk: there
+      // the increments are far below half an ulp of 1 and would be lost on phi itself
+      if (y0) out = yn0 + b1 * ((own - yn0) + dt * Lphi);
     } else {
       if (y0) out = a0 * yn0 + b1 * ys;
     }
@@ -842,15 +870,15 @@ __global__ __launch_bounds__(Tile<TY>::NT) __attribute__((amdgpu_waves_per_eu(
 // h_{a+2} at the faces a+1/2, a = q-2 .. q+1, weighted by rc.l4 with (1, -27, 27, -1)), the
 // five-point fourth-order difference along phi.
 template <typename T>
-__device__ __forceinline__ T lap4_at(const T* h, const RowCoef<T>& rc, int q, int s, int nt,
-                                     int np) {
+__device__ __forceinline__ T lap4_at(const T* h, const T* hb, const RowCoef<T>& rc, int q,
+                                     int s, int nt, int np) {
   T c[7];  // rows q-3 .. q+3 of column s
 #pragma unroll
-  for (int o = -3; o <= 3; ++o) c[o + 3] = h[(long long)wrapi(q + o, nt) * np + s];
+  for (int o = -3; o <= 3; ++o) c[o + 3] = phi_val(h, hb, (long long)wrapi(q + o, nt) * np + s);
   auto G = [&](int o) { return c[o + 2] - T(27) * c[o + 3] + T(27) * c[o + 4] - c[o + 5]; };
   const long long row = (long long)q * np;
-  const T e1 = h[row + wrapi(s + 1, np)], e2 = h[row + wrapi(s + 2, np)];
-  const T w1 = h[row + wrapi(s - 1, np)], w2 = h[row + wrapi(s - 2, np)];
+  const T e1 = phi_val(h, hb, row + wrapi(s + 1, np)), e2 = phi_val(h, hb, row + wrapi(s + 2, np));
+  const T w1 = phi_val(h, hb, row + wrapi(s - 1, np)), w2 = phi_val(h, hb, row + wrapi(s - 2, np));
   const T lap_th = rc.l4[0] * G(-2) - T(27) * (rc.l4[1] * G(-1)) + T(27) * (rc.l4[2] * G(0)) -
                    rc.l4[3] * G(1);
   const T lap_ph = rc.lp4 * ((-w2 + T(16) * w1) - T(30) * c[3] + (T(16) * e1 - e2));
@@ -874,8 +902,8 @@ __global__ __launch_bounds__(256) void tlb_ch4_prep_kernel(Ch4Args<T> a) {
   if constexpr (stores_deviation<T>()) n += a.n_ref;
   const T inv_n = recip(n);
   const RowCoef<T> rc = a.rows[q];
-  const T ph = a.phi[x];
-  a.mu[x] = a.A * ph * (ph * ph - T(1)) - a.kappa * lap4_at(a.phi, rc, q, s, a.nt, a.np);
+  const T ph = phi_val(a.phi, a.phib, x);
+  a.mu[x] = a.A * ph * (ph * ph - T(1)) - a.kappa * lap4_at(a.phi, a.phib, rc, q, s, a.nt, a.np);
   a.P[x] = rc.J * (nut * inv_n) * ph;
   a.Q[x] = (nup * inv_n) * ph;
 }
@@ -948,13 +976,14 @@ __global__ __launch_bounds__(256) void tlb_offset_kernel(T* f, long long plane, 
 // one (several waves may store the same value).
 template <typename T>
 __global__ __launch_bounds__(256) void tlb_nonfinite_kernel(const T* f, const T* phi,
-                                                           long long plane, int* flag) {
+                                                           const T* phib, long long plane,
+                                                           int* flag) {
   bool bad = false;
   for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < plane;
        x += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) bad = bad || !isfinite(f[k * plane + x]);
-    bad = bad || !isfinite(phi[x]);
+    bad = bad || !isfinite(phi[x]) || (phib && !isfinite(phib[x]));
   }
   if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) *flag = 1;
 }
@@ -962,9 +991,39 @@ __global__ __launch_bounds__(256) void tlb_nonfinite_kernel(const T* f, const T*
 // *flag = value (a kernel, not a memset: the step loop may be captured into a graph)
 __global__ void tlb_set_flag_kernel(int* flag, int value) { *flag = value; }
 
+// FP32 order parameter, stored as base b + deviation d: move the deviation into the base,
+// exactly -- b' = fl(b + d) and d' = (b + d) - b', the rounding error of that sum, by the
+// error-free two-sum (Knuth) -- so that d stays small (a few ulps of b) and the small
+// increments it accumulates keep their precision.  b' + d' = b + d.
+// (one by-value argument block, so that it can be a graph node like the stage kernels)
+struct RebaseArgs {
+  float* b;
+  float* d;
+  long long plane;
+};
+
+__global__ __launch_bounds__(256) void tlb_phi_rebase_kernel(RebaseArgs a) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.plane) return;
+  const float bb = a.b[x], dd = a.d[x];
+  const float sum = bb + dd;
+  const float bv = sum - dd;  // the part of sum that came from bb
+  const float dv = sum - bv;  // ... and from dd
+  a.b[x] = sum;
+  a.d[x] = (bb - bv) + (dd - dv);
+}
+
+// out = b + d (FP32 order parameter as one plane; out may alias neither)
+__global__ __launch_bounds__(256) void tlb_phi_sum_kernel(float* out, const float* b,
+                                                         const float* d, long long plane) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < plane) out[x] = b[x] + d[x];
+}
+
 // moments and chemical potential of a state, one thread per node
 template <typename T>
-__global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* phi, T* n_out,
+__global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* phi,
+                                                         const T* phib, T* n_out,
                                                          T* ut_out, T* up_out, T* phi_out,
                                                          T* mu_out, const RowCoef<T>* rows,
                                                          int nt, int np, T A, T kappa,
@@ -985,17 +1044,18 @@ __global__ __launch_bounds__(256) void tlb_moments_kernel(const T* f, const T* p
   if (n_out) n_out[x] = n;
   if (ut_out) ut_out[x] = nut / n;
   if (up_out) up_out[x] = nup / n;
-  const T ph = phi[x];
+  const T ph = phi_val(phi, phib, x);
   if (phi_out) phi_out[x] = ph;
   if (mu_out && ch4) {
-    mu_out[x] = A * ph * (ph * ph - T(1)) - kappa * lap4_at(phi, rows[q], q, s, nt, np);
+    mu_out[x] = A * ph * (ph * ph - T(1)) - kappa * lap4_at(phi, phib, rows[q], q, s, nt, np);
   } else if (mu_out) {
     const RowCoef<T>& rc = rows[q];
     const int qn = q + 1 == nt ? 0 : q + 1, qs = q == 0 ? nt - 1 : q - 1;
     const int se = s + 1 == np ? 0 : s + 1, sw = s == 0 ? np - 1 : s - 1;
-    const T lap = rc.lap_n * (phi[(long long)qn * np + s] - ph) -
-                  rc.lap_s * (ph - phi[(long long)qs * np + s]) +
-                  rc.lap_p * (phi[(long long)q * np + se] - T(2) * ph + phi[(long long)q * np + sw]);
+    const T lap = rc.lap_n * (phi_val(phi, phib, (long long)qn * np + s) - ph) -
+                  rc.lap_s * (ph - phi_val(phi, phib, (long long)qs * np + s)) +
+                  rc.lap_p * (phi_val(phi, phib, (long long)q * np + se) - T(2) * ph +
+                              phi_val(phi, phib, (long long)q * np + sw));
     mu_out[x] = A * ph * (ph * ph - T(1)) - kappa * lap;
   }
 }
@@ -1012,6 +1072,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, const T* phi,
+                                                                const T* phib,
                                                                 const double* area, int nt,
                                                                 int np, int rows_per_block,
                                                                 double n_add, double* partial) {
@@ -1032,7 +1093,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, con
         n += fk;
       }
       n += n_add;  // the reference density of deviation storage (else 0)
-      const double ph = (double)phi[x];
+      const double ph = phi_val64(phi, phib, x);
       bad += isfinite(ph) ? 0.0 : 1.0;
       rm += n;
       rp += ph;
@@ -1063,6 +1124,7 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_reduce_kernel(const T* f, con
 // and the area, as partials for tlb_reduce_final_kernel.
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const T* phi,
+                                                              const T* phib,
                                                               const double* area,
                                                               const double* half_len, double r_dth,
                                                               double A, int nt, int np,
@@ -1080,9 +1142,9 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
     for (int s0 = threadIdx.x; s0 < np; s0 += RED_THREADS) {
       const long long x = (long long)q * np + s0;
       const int se = s0 + 1 == np ? 0 : s0 + 1;
-      const double ph = (double)phi[x];
-      if (ph * (double)phi[(long long)q * np + se] < 0.0) len += r_dth;
-      if (ph * (double)phi[(long long)qn * np + s0] < 0.0) len += half_len[q];
+      const double ph = phi_val64(phi, phib, x);
+      if (ph * phi_val64(phi, phib, (long long)q * np + se) < 0.0) len += r_dth;
+      if (ph * phi_val64(phi, phib, (long long)qn * np + s0) < 0.0) len += half_len[q];
       double n = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) n += (double)f[k * plane + x];
@@ -1127,13 +1189,13 @@ __global__ __launch_bounds__(RED_THREADS) void tlb_diag_kernel(const T* f, const
 // left out, so the mean of phi need not be removed.  tw holds exp(-2 pi i j / n) for the row
 // length n_phi followed by the column length n_theta.
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void tlb_dft_rows_kernel(const T* phi,
+__global__ __launch_bounds__(RED_THREADS) void tlb_dft_rows_kernel(const T* phi, const T* phib,
                                                                   const double2* tw, double2* X,
                                                                   int np) {
   extern __shared__ double srow[];  // the row, n_phi values
   const int q = blockIdx.x;
   for (int s0 = threadIdx.x; s0 < np; s0 += RED_THREADS)
-    srow[s0] = (double)phi[(long long)q * np + s0];
+    srow[s0] = phi_val64(phi, phib, (long long)q * np + s0);
   __syncthreads();
   for (int m = threadIdx.x; m < np; m += RED_THREADS) {
     double re = 0.0, im = 0.0;
@@ -1314,6 +1376,7 @@ StageArgs<T> stage_args(const tlb_grid* g, int stage) {
   a.a0 = stage == 2 ? T(0.75) : stage == 3 ? T(1.0 / 3.0) : T(0);
   a.b1 = stage == 2 ? T(0.25) : stage == 3 ? T(2.0 / 3.0) : T(1);
   a.c = make_consts<T>(g->p, g->n_ref);
+  if constexpr (stores_deviation<T>()) a.phib = reinterpret_cast<const T*>(g->phi_base);
   if (g->ch4) {
     const T* w = static_cast<const T*>(g->ch4);
     a.mu4 = w;
@@ -1432,6 +1495,7 @@ int stage_launches(const tlb_grid* g, int stage, tlbi_launch out[2]) {
     Ch4Args<T> c{};
     c.f = a.fin;
     c.phi = a.phin;
+    c.phib = a.phib;
     c.mu = const_cast<T*>(a.mu4);
     c.P = const_cast<T*>(a.P4);
     c.Q = const_cast<T*>(a.Q4);
@@ -1502,9 +1566,9 @@ hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_pa
 }
 
 // A chain of `steps` time steps of the grid's stage launches (kernel nodes only), each node
-// depending on the one before.
+// depending on the one before, closed by the rebase of the order parameter if `close`.
 template <typename T>
-int32_t build_step_graph(tlb_grid* g, int steps) {
+int32_t build_step_graph(tlb_grid* g, int steps, bool close) {
   tlbi_launch l[3][2];
   int n[3];
   void* argp[3][2];
@@ -1516,34 +1580,55 @@ int32_t build_step_graph(tlb_grid* g, int steps) {
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
   hipGraphNode_t prev = nullptr;
+  auto add = [&](const tlbi_launch& l, void** params) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(l.fn);
+    kp.gridDim = l.grid;
+    kp.blockDim = l.block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  };
   for (int t = 0; t < steps && e == hipSuccess; ++t)
     for (int st = 0; st < 3 && e == hipSuccess; ++st)
-      for (int i = 0; i < n[st] && e == hipSuccess; ++i) {
-        hipKernelNodeParams kp{};
-        kp.func = const_cast<void*>(l[st][i].fn);
-        kp.gridDim = l[st][i].grid;
-        kp.blockDim = l[st][i].block;
-        kp.sharedMemBytes = 0;
-        kp.kernelParams = &argp[st][i];
-        kp.extra = nullptr;
-        hipGraphNode_t node;
-        e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-        prev = node;
-      }
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->graphs[steps], graph, nullptr, nullptr, 0);
+      for (int i = 0; i < n[st] && e == hipSuccess; ++i) add(l[st][i], &argp[st][i]);
+  tlbi_launch rb;
+  void* rbp = rb.args;
+  if (e == hipSuccess && close && tlbi_phi_rebase_launch(g, &rb)) add(rb, &rbp);
+  hipGraphExec_t& slot = g->graphs[close ? 1 : 0][steps];
+  if (e == hipSuccess) e = hipGraphInstantiate(&slot, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    g->graphs[steps] = nullptr;
+    slot = nullptr;
     return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
   }
   return TLB_OK;
 }
 
 void drop_graph(tlb_grid* g) {
-  for (hipGraphExec_t& x : g->graphs) {
-    if (x) (void)hipGraphExecDestroy(x);
-    x = nullptr;
-  }
+  for (auto& row : g->graphs)
+    for (hipGraphExec_t& x : row) {
+      if (x) (void)hipGraphExecDestroy(x);
+      x = nullptr;
+    }
+}
+
+// The next run of at most `n` steps of grid g: its length, and whether it ends on a rebase of
+// the order parameter (FP32 grids rebase after every GRAPH_CHUNK-th step since set_state).
+struct Run {
+  int steps;
+  bool close;
+};
+Run next_run(const tlb_grid* g, int64_t n) {
+  const int left = GRAPH_CHUNK - g->phase;
+  const int s = (int)std::min<int64_t>(left, n);
+  return Run{s, g->phi_base != nullptr && s == left};
+}
+void advance_phase(tlb_grid* g, int steps) {
+  g->phase = g->phi_base ? (g->phase + steps) % GRAPH_CHUNK : 0;
 }
 
 template <typename T>
@@ -1551,8 +1636,8 @@ int32_t check_t(tlb_grid* g) {
   const long long plane = (long long)g->p.n_theta * g->p.n_phi;
   const int blocks = (int)std::min<long long>(4096, (plane + 255) / 256);
   hipLaunchKernelGGL(tlb_nonfinite_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
-                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]), plane,
-                     g->check_flag);
+                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]),
+                     reinterpret_cast<const T*>(g->phi_base), plane, g->check_flag);
   TLB_HIP_CHECK(hipGetLastError());
   return TLB_OK;
 }
@@ -1563,22 +1648,29 @@ int32_t step_n_t(tlb_grid* g, int64_t n) {
     drop_graph(g);
     g->graph_version = g->version;
   }
-  if (g->p.flags & TLB_NO_GRAPH) {
-    for (int64_t done = 0; done < n; ++done)
-      for (int st = 1; st <= 3; ++st) {
-        int32_t rc = launch_stage<T>(g, st);
+  const bool direct = g->p.flags & TLB_NO_GRAPH;  // the same runs as the graphs, launch by launch
+  for (int64_t done = 0; done < n;) {
+    const Run r = next_run(g, n - done);
+    if (direct) {
+      for (int t = 0; t < r.steps; ++t)
+        for (int st = 1; st <= 3; ++st) {
+          int32_t rc = launch_stage<T>(g, st);
+          if (rc != TLB_OK) return rc;
+        }
+      if (r.close) {
+        int32_t rc = tlbi_phi_rebase(g, g->stream);
         if (rc != TLB_OK) return rc;
       }
-    return TLB_OK;
-  }
-  for (int64_t done = 0; done < n;) {
-    const int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);
-    if (!g->graphs[s]) {
-      int32_t rc = build_step_graph<T>(g, s);
-      if (rc != TLB_OK) return rc;
+    } else {
+      hipGraphExec_t& x = g->graphs[r.close ? 1 : 0][r.steps];
+      if (!x) {
+        int32_t rc = build_step_graph<T>(g, r.steps, r.close);
+        if (rc != TLB_OK) return rc;
+      }
+      TLB_HIP_CHECK(hipGraphLaunch(x, g->stream));
     }
-    TLB_HIP_CHECK(hipGraphLaunch(g->graphs[s], g->stream));
-    done += s;
+    advance_phase(g, r.steps);
+    done += r.steps;
   }
   return TLB_OK;
 }
@@ -1717,7 +1809,8 @@ int32_t batch_launch_t(tlb_batch* b, int stage) {
 template <typename T>
 int32_t batch_step_t(tlb_batch* b, int64_t n) {
   for (int64_t done = 0; done < n;) {
-    const int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);
+    int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);  // up to the next rebase of any grid
+    for (int i = 0; i < b->n; ++i) s = std::min(s, next_run(b->grids[i], s).steps);
     if (!b->graphs[s]) {
       const void* fn = batch_fn<T>(b);
       const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
@@ -1733,6 +1826,15 @@ int32_t batch_step_t(tlb_batch* b, int64_t n) {
         return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
     }
     TLB_HIP_CHECK(hipGraphLaunch(b->graphs[s], b->stream));
+    for (int i = 0; i < b->n; ++i) {  // each grid rebases where it would when stepped alone
+      tlb_grid* g = b->grids[i];
+      const bool close = next_run(g, s).close;
+      advance_phase(g, s);
+      if (close) {
+        int32_t rc = tlbi_phi_rebase(g, b->stream);
+        if (rc != TLB_OK) return rc;
+      }
+    }
     done += s;
   }
   return TLB_OK;
@@ -1793,6 +1895,7 @@ int32_t moments_t(tlb_grid* g, void* n, void* ut, void* up, void* phi, void* mu)
   const int blocks = (int)((plane + 255) / 256);
   hipLaunchKernelGGL(tlb_moments_kernel<T>, dim3(blocks), dim3(256), 0, g->stream,
                      static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]),
+                     reinterpret_cast<const T*>(g->phi_base),
                      static_cast<T*>(n), static_cast<T*>(ut), static_cast<T*>(up),
                      static_cast<T*>(phi), static_cast<T*>(mu),
                      static_cast<const RowCoef<T>*>(g->rows), g->p.n_theta, g->p.n_phi,
@@ -1807,7 +1910,8 @@ template <typename T>
 int32_t reduce_t(tlb_grid* g, double n_add) {
   hipLaunchKernelGGL(tlb_reduce_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0,
                      g->stream, static_cast<const T*>(g->f[0]),
-                     static_cast<const T*>(g->phi[0]), g->area, g->p.n_theta, g->p.n_phi,
+                     static_cast<const T*>(g->phi[0]), reinterpret_cast<const T*>(g->phi_base),
+                     g->area, g->p.n_theta, g->p.n_phi,
                      g->rows_per_block, n_add, g->partial);
   TLB_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(tlb_reduce_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream,
@@ -1820,7 +1924,8 @@ template <typename T>
 int32_t diag_t(tlb_grid* g, double* phi_avg, double* p_avg) {
   const double dth = 2.0 * M_PI / g->p.n_theta;
   hipLaunchKernelGGL(tlb_diag_kernel<T>, dim3(g->red_blocks), dim3(RED_THREADS), 0, g->stream,
-                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]), g->area,
+                     static_cast<const T*>(g->f[0]), static_cast<const T*>(g->phi[0]),
+                     reinterpret_cast<const T*>(g->phi_base), g->area,
                      g->half_len, g->p.r * dth, g->p.A, g->p.n_theta, g->p.n_phi,
                      g->rows_per_block, stores_deviation<T>() ? g->n_ref : 0.0, phi_avg, p_avg,
                      g->partial);
@@ -1903,6 +2008,28 @@ std::atomic<unsigned long long> g_next_uid{1};
 // ------------------------------------------------------------------------------------------
 int32_t tlbi_fail(int32_t code, const std::string& msg) { return fail(code, msg); }
 
+int tlbi_phi_rebase_launch(const tlb_grid* g, tlbi_launch* out) {
+  if (!g->phi_base) return 0;
+  const RebaseArgs args{g->phi_base, static_cast<float*>(g->phi[0]),
+                        (long long)g->p.n_theta * g->p.n_phi};
+  static_assert(sizeof(args) <= sizeof(out->args), "argument block");
+  out->fn = reinterpret_cast<const void*>(&tlb_phi_rebase_kernel);
+  out->grid = dim3((unsigned)((args.plane + 255) / 256));
+  out->block = dim3(256);
+  std::memcpy(out->args, &args, sizeof(args));
+  return 1;
+}
+
+int32_t tlbi_phi_rebase(const tlb_grid* g, hipStream_t stream) {
+  if (!g->phi_base) return TLB_OK;
+  const RebaseArgs args{g->phi_base, static_cast<float*>(g->phi[0]),
+                        (long long)g->p.n_theta * g->p.n_phi};
+  hipLaunchKernelGGL(tlb_phi_rebase_kernel, dim3((unsigned)((args.plane + 255) / 256)), dim3(256),
+                     0, stream, args);
+  TLB_HIP_CHECK(hipGetLastError());
+  return TLB_OK;
+}
+
 int tlbi_stage_launches(const tlb_grid* g, int stage, tlbi_launch out[2]) {
   return g->p.precision == 64 ? stage_launches<double>(g, stage, out)
                               : stage_launches<float>(g, stage, out);
@@ -1943,7 +2070,8 @@ int32_t structure_t(tlb_grid* g, double out[3]) {
   tw = X + (size_t)nt * np;
   part = reinterpret_cast<double*>(tw + np + nt);
   hipLaunchKernelGGL(tlb_dft_rows_kernel<T>, dim3(nt), dim3(RED_THREADS), np * sizeof(double),
-                     g->stream, static_cast<const T*>(g->phi[0]), tw, X, np);
+                     g->stream, static_cast<const T*>(g->phi[0]),
+                     reinterpret_cast<const T*>(g->phi_base), tw, X, np);
   TLB_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(tlb_dft_cols_kernel, dim3(np), dim3(RED_THREADS), nt * sizeof(double2),
                      g->stream, X, tw + np, nt, np, g->p.r, g->p.R, part);
@@ -2059,7 +2187,8 @@ int32_t structure_noalloc_t(tlb_grid* g, double out[3]) {
   hipLaunchKernelGGL(tlb_twiddle_kernel, dim3((np + nt + RED_THREADS - 1) / RED_THREADS),
                      dim3(RED_THREADS), 0, g->stream, tw, np, nt);
   hipLaunchKernelGGL(tlb_dft_rows_kernel<T>, dim3(nt), dim3(RED_THREADS), np * sizeof(double),
-                     g->stream, static_cast<const T*>(g->phi[0]), tw, X, np);
+                     g->stream, static_cast<const T*>(g->phi[0]),
+                     reinterpret_cast<const T*>(g->phi_base), tw, X, np);
   hipLaunchKernelGGL(tlb_dft_cols_kernel, dim3(np), dim3(RED_THREADS), nt * sizeof(double2),
                      g->stream, X, tw + np, nt, np, g->p.r, g->p.R, part);
   hipLaunchKernelGGL(tlb_structure_final_kernel, dim3(1), dim3(RED_THREADS), 0, g->stream, part,
@@ -2145,6 +2274,7 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
     if (g->check_flag) (void)hipFree(g->check_flag);
     if (g->proj) (void)hipFree(g->proj);
     if (g->ch4) (void)hipFree(g->ch4);
+    if (g->phi_base) (void)hipFree(g->phi_base);
     delete g;
     return fail(code, msg);
   };
@@ -2164,6 +2294,8 @@ int32_t tlb_create_torus_grid(const tlb_params* params, const tlb_buffers* buffe
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->proj), sizeof(double) * 3 * nt);
   if (e == hipSuccess && (params->flags & TLB_CH4))
     e = hipMalloc(&g->ch4, 3 * (size_t)nt * params->n_phi * g->elem);
+  if (e == hipSuccess && params->precision == 32)
+    e = hipMalloc(reinterpret_cast<void**>(&g->phi_base), (size_t)nt * params->n_phi * sizeof(float));
   if (e != hipSuccess)
     return cleanup(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipMemcpyAsync(g->rows, host_rows, row_bytes * nt, hipMemcpyHostToDevice, g->stream);
@@ -2193,6 +2325,7 @@ void tlb_destroy(tlb_grid* g) {
   (void)hipFree(g->check_flag);
   (void)hipFree(g->proj);
   if (g->ch4) (void)hipFree(g->ch4);
+  if (g->phi_base) (void)hipFree(g->phi_base);
   delete g;
 }
 
@@ -2202,7 +2335,14 @@ int32_t tlb_set_state(tlb_grid* g, const void* f, const void* phi, const void* n
   if (!g || !phi) return fail(TLB_EINVAL, "grid or phi is NULL");
   if (!f && (!n || !ut || !up)) return fail(TLB_EINVAL, "f is NULL and a moment field is NULL");
   const size_t plane_bytes = (size_t)g->p.n_theta * g->p.n_phi * g->elem;
-  TLB_HIP_CHECK(hipMemcpyAsync(g->phi[0], phi, plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  g->phase = 0;
+  if (g->phi_base) {  // FP32: phi becomes the base, its deviation zero
+    TLB_HIP_CHECK(
+        hipMemcpyAsync(g->phi_base, phi, plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+    TLB_HIP_CHECK(hipMemsetAsync(g->phi[0], 0, plane_bytes, g->stream));
+  } else {
+    TLB_HIP_CHECK(hipMemcpyAsync(g->phi[0], phi, plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  }
   if (f) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(g->f[0], f, 16 * plane_bytes, hipMemcpyDeviceToDevice, g->stream));
@@ -2284,9 +2424,16 @@ int32_t tlb_get_state(tlb_grid* g, void* f, void* phi) {
       if (rc != TLB_OK) return rc;
     }
   }
-  if (phi)
+  if (phi && g->phi_base) {  // FP32: base + deviation
+    const long long plane = (long long)g->p.n_theta * g->p.n_phi;
+    hipLaunchKernelGGL(tlb_phi_sum_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0,
+                       g->stream, static_cast<float*>(phi), g->phi_base,
+                       static_cast<const float*>(g->phi[0]), plane);
+    TLB_HIP_CHECK(hipGetLastError());
+  } else if (phi) {
     TLB_HIP_CHECK(
         hipMemcpyAsync(phi, g->phi[0], plane_bytes, hipMemcpyDeviceToDevice, g->stream));
+  }
   return TLB_OK;
 }
 

@@ -27,9 +27,10 @@ struct tlb_grid {
   int red_blocks, rows_per_block;
   size_t elem;
   int ty;                     // tile height of the stage kernel (4, 8 or 16)
-  // graphs[s]: s = 1..TLBI_GRAPH_CHUNK time steps as one graph of kernel nodes, each built on
-  // the first call that needs it; graph_version: the grid's version when they were built
-  hipGraphExec_t graphs[TLBI_GRAPH_CHUNK + 1];
+  // graphs[c][s]: s = 1..TLBI_GRAPH_CHUNK time steps as one graph of kernel nodes, closed by the
+  // rebase of the order parameter when c = 1 (FP32), each built on the first call that needs it;
+  // graph_version: the grid's version when they were built
+  hipGraphExec_t graphs[2][TLBI_GRAPH_CHUNK + 1];
   unsigned graph_version;
   void* dft_work;  // structure-factor workspace (built on first use): row transforms and twiddles
   double n_ref;      // reference density of FP32 storage (see stores_deviation), a float value
@@ -38,7 +39,14 @@ struct tlb_grid {
   int* check_flag;   // [1]: set by the non-finite check of tlb_step_n (check_every > 0)
   double* proj;      // [3 nt]: per-row sums of the learned correction (tlb_apply_correction)
   void* ch4;         // TLB_CH4: mu, J u^theta phi, u^phi phi of a stage input (3 planes of T)
+  // FP32 grids: the order parameter is phi_base + phi[c] (c = 0, 1, 2 hold deviations from the
+  // base); the deviation of copy 0 moves into the base after every TLBI_GRAPH_CHUNK-th time step
+  // counted from the last set_state, so the bits of a state do not depend on how the steps that
+  // made it were split into calls
+  float* phi_base;
+  int phase;  // FP32: time steps since the last rebase (0 .. TLBI_GRAPH_CHUNK - 1); FP64: 0
 };
+
 
 // Records `msg` as the thread's last error and returns `code`.
 int32_t tlbi_fail(int32_t code, const std::string& msg);
@@ -49,6 +57,12 @@ struct tlbi_launch {
   dim3 grid, block;
   alignas(16) unsigned char args[512];
 };
+
+// FP32 grids: move the deviation of state copy 0 into the order parameter's base (exactly),
+// enqueued on `stream`; no-op for FP64 grids.
+int32_t tlbi_phi_rebase(const tlb_grid* g, hipStream_t stream);
+// the rebase as a launch record (FP32 grids); returns 0 for FP64 grids, else 1
+int tlbi_phi_rebase_launch(const tlb_grid* g, tlbi_launch* out);
 
 // The launches of Runge-Kutta stage `stage` (1..3) of one time step of grid g (the stage
 // kernel, preceded by a prepass for TLB_CH4); returns their number (1 or 2).

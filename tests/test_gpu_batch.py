@@ -84,6 +84,20 @@ def test_batch_equals_grids_stepped_alone(torch_cuda, precision):
     batch.step(33)
     for g, h in zip(alone, batched):
         assert torch_cuda.equal(g.get_state()[0], h.get_state()[0])
+    # grids that were stepped alone before joining a batch: FP32 grids fold the order
+    # parameter's deviation into its base on their own step counts, inside the batch too
+    alone[0].step(5)
+    batched[0].step(5)
+    alone[1].step(19)
+    batched[1].step(19)
+    for g in alone:
+        g.step(40)
+    batch.step(40)
+    torch_cuda.cuda.synchronize()
+    for g, h in zip(alone, batched):
+        fa, pa = g.get_state()
+        fb, pb = h.get_state()
+        assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb)
 
 
 def test_new_reference_density_reaches_graphs_and_batches(torch_cuda):

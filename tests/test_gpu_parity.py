@@ -216,15 +216,16 @@ def test_roofline_size_streaming_fp64_and_fp32(torch_cuda):
     assert e32f <= 1e-5 and e32p <= 1e-5
 
 
-def test_graph_replay_matches_plain_launches_bitwise(torch_cuda):
+@pytest.mark.parametrize("precision", [64, 32])
+def test_graph_replay_matches_plain_launches_bitwise(torch_cuda, precision):
     """tlb_step_n replays a prebuilt graph of 32 steps; with TLB_NO_GRAPH it launches each
     kernel.  Several replays, with eager work and synchronisation between them, must give
     bit-identical states."""
     from paper_1904_10070_amd import TorusGrid, NO_GRAPH
     p = inputs.TorusParams(1.0, 2.5, 40, 96, 0.5, 2e-3, 0.05, 0.3, 2e-4)
     phi, n, ut, up = inputs.random_state(p, seed=17)
-    a = TorusGrid(p, precision=64)
-    b = TorusGrid(p.with_(flags=NO_GRAPH), precision=64)
+    a = TorusGrid(p, precision=precision)
+    b = TorusGrid(p.with_(flags=NO_GRAPH), precision=precision)
     for g in (a, b):
         g.set_state(phi, n, ut, up)
     for call in range(5):
@@ -235,6 +236,28 @@ def test_graph_replay_matches_plain_launches_bitwise(torch_cuda):
         fa, pa = a.get_state()
         fb, pb = b.get_state()
         assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb), call
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_fp32_state_does_not_depend_on_how_steps_are_split(torch_cuda, flags):
+    """FP32 grids keep the order parameter as a base plus a deviation and fold the deviation
+    into the base after every 32nd step since set_state.  That schedule counts steps, not
+    calls: 100 steps in one call and the same 100 steps in calls of 7, 45 and 48 (graph
+    replays, flags 0, or launch by launch, flags 4 = TLB_NO_GRAPH) give the same bits."""
+    from paper_1904_10070_amd import TorusGrid
+    p = inputs.TorusParams(1.0, 2.5, 40, 96, 0.5, 2e-3, 0.05, 0.3, 2e-4)
+    state = inputs.random_state(p, seed=23)
+    a = TorusGrid(p, precision=32)
+    b = TorusGrid(p.with_(flags=flags), precision=32)
+    for g in (a, b):
+        g.set_state(*state)
+    a.step(100)
+    for k in (7, 45, 48):
+        b.step(k)
+    fa, pa = a.get_state()
+    fb, pb = b.get_state()
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(fa, fb) and torch_cuda.equal(pa, pb)
 
 
 @pytest.mark.parametrize("shape,flags", [((64, 160), 8), ((37, 150), 8), ((9, 70), 8 | 1),
