@@ -130,7 +130,10 @@ int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections);
 
 /* n_steps learned coarse steps: each is one tlb_step_n step of the grid followed by the
  * network's correction of the result.  The grid must match the network's n_theta, n_phi.
- * Runs of 32 steps replay a prebuilt graph unless the grid has TLB_NO_GRAPH.               */
+ * The network of a step runs as one launch that forms the moments itself (tiles with a
+ * five-node halo, activations on chip); the corrections it applies are bit for bit those of
+ * tlb_cnn_forward on the moments from tlb_learn_pair.  Runs of 32 steps replay a prebuilt
+ * graph unless the grid has TLB_NO_GRAPH.                                                  */
 int32_t tlb_learned_step_n(tlb_grid* grid, tlb_cnn* net, int64_t n_steps);
 
 #ifdef __cplusplus

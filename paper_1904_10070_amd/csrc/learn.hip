@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -635,6 +636,8 @@ template <typename T>
 struct ApplyArgs {
   T* f;
   T* phi;
+  T* phib;                  // FP32 grids in the learned step: fold phi into this base after
+                            // the correction (exact two-sum); NULL: phi itself is corrected
   const float* d;           // corrections [HW][4], times scale
   const double* partial;    // [nparts][3]: sum a dphi, sum a dn, sum a
   int nparts;
@@ -694,7 +697,179 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs<T> a) {
     a.f[k * a.plane + x] =
         fk[k] + (feq_k<T>(k >> 2, k & 3, n + dn, ut + dut, up + dup) - feq_k<T>(k >> 2, k & 3, n, ut, up));
   });
-  a.phi[x] += dphi;
+  const T dev = a.phi[x] + dphi;
+  if (a.phib) {  // base + dev = sum + err exactly (two-sum); the base takes the sum
+    const T bb = a.phib[x];
+    const T sum = bb + dev;
+    const T bv = sum - dev;
+    const T dv = sum - bv;
+    a.phib[x] = sum;
+    a.phi[x] = (bb - bv) + (dev - dv);
+  } else {
+    a.phi[x] = dev;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// the network of a learned step in one launch
+//
+// One workgroup per output tile of NT_H x NT_W nodes.  It forms the moments and input features
+// of the tile and of a five-node halo around it (the reach of five 3x3 layers) straight from
+// the grid's state, then runs the five layers through LDS: layer l produces the tile plus a
+// halo of 4 - l nodes, reading only what the layer before it wrote.  Halo nodes are computed by
+// every tile that needs them (about twice the matrix work of the layer-by-layer kernels); in
+// exchange the step's network is one launch instead of six and its activations never reach
+// HBM.  Products, their order and every bfloat16 rounding are those of conv_kernel (and the
+// moments those of moments_pair_kernel), so the output is the same bit for bit.
+
+constexpr int NT_H = 8, NT_W = 24;   // output tile
+constexpr int NT_G = 2;              // 16-node groups per layer row
+constexpr int NT_PW = 16 * NT_G + 2; // row pitch of the LDS planes in nodes: the groups + 2 read
+constexpr int NT_THREADS = 512;
+constexpr int NT_WAVES = NT_THREADS / 64;
+static_assert(NT_W + 8 <= 16 * NT_G, "layer 0 row of the tile and its halo in NT_G groups");
+static_assert(NT_W + 10 <= NT_PW, "feature row of the tile and its halo");
+// fragment offsets of the layers in the staged weights (bf16x8 units)
+constexpr int nt_frags(int l) { return (L_CIS[l] == 32 ? 9 : 3) * ((L_COUT[l] + 15) / 16) * 64; }
+constexpr int nt_frag_offset(int l) { return l == 0 ? 0 : nt_frag_offset(l - 1) + nt_frags(l - 1); }
+constexpr int NT_FRAGS = nt_frag_offset(NL);
+
+template <typename T>
+struct NetArgs {
+  const T* f;
+  const T* phi;
+  const T* phib;   // base of phi (FP32) or NULL
+  long long plane;
+  double n_add;    // what a node's population sum lacks of its density
+  const bf16x8* w[NL];  // forward weight fragments of each layer
+  const float* bias[NL];
+  Features F;
+  int H, W, tiles_x;
+  float* out;      // [H][W][4]: network output
+  double* proj;    // [block][3]: sum a z0 s0, sum a z1 s1, sum a over the tile
+  const double* area;
+  float s0, s1;
+};
+
+// One layer over the tile: rows `rows` of 16 NT_G-node groups, input plane `in` (features,
+// 8 channels, when IN8; else 32-channel activations), output plane `out` (32 channels) or,
+// for the last layer, the network output in HBM.
+template <bool IN8, int COB, bool LAST, typename T>
+__device__ __forceinline__ void nt_layer(const NetArgs<T>& a, const bf16x8* sw, const void* in,
+                                         u16* out, int l, int rows, int y0, int x0,
+                                         double (&ps)[3]) {
+  constexpr int KC = IN8 ? 3 : 9;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int px = lane & 15, g = lane >> 4;
+  bf16x8 wa[KC][COB];
+#pragma unroll
+  for (int c = 0; c < KC; ++c)
+#pragma unroll
+    for (int b = 0; b < COB; ++b) wa[c][b] = sw[(c * COB + b) * 64 + lane];
+  const float* bias = a.bias[l];
+  for (int u = wave; u < rows * NT_G; u += NT_WAVES) {
+    const int i = u / NT_G, col = (u % NT_G) * 16 + px;
+    bf16x8 bf[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int tap = IN8 ? 4 * c + g : c;
+      if (tap < 9) {
+        const int node = (i + tap / 3) * NT_PW + col + tap % 3;
+        bf[c] = IN8 ? static_cast<const bf16x8*>(in)[node]
+                    : static_cast<const bf16x8*>(in)[node * 4 + g];
+      } else {
+        bf[c] = zero_frag();
+      }
+    }
+    f32x4 acc[COB];
+#pragma unroll
+    for (int b = 0; b < COB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+#pragma unroll
+      for (int b = 0; b < COB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c][b], bf[c], acc[b], 0, 0, 0);
+    // lane holds node col of row i, output channels 16 b + 4 g + k
+    if constexpr (LAST) {
+      const int y = y0 + i, x = x0 + col;
+      if (g == 0 && col < NT_W && y < a.H && x < a.W) {
+        float4 o;
+        o.x = acc[0][0] + bias[0];
+        o.y = acc[0][1] + bias[1];
+        o.z = acc[0][2] + bias[2];
+        o.w = acc[0][3] + bias[3];
+        reinterpret_cast<float4*>(a.out)[(size_t)y * a.W + x] = o;
+        if (a.proj) {
+          const double ar = a.area[y];
+          ps[0] += ar * (double)(o.x * a.s0);
+          ps[1] += ar * (double)(o.y * a.s1);
+          ps[2] += ar;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < COB; ++b) {
+        const int co = 16 * b + 4 * g;
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = fmaxf(acc[b][k] + bias[co + k], 0.0f);
+        uint2 st;
+        st.x = (unsigned)to_bf16(v[0]) | ((unsigned)to_bf16(v[1]) << 16);
+        st.y = (unsigned)to_bf16(v[2]) | ((unsigned)to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2*>(out + (size_t)(i * NT_PW + col) * 32 + co) = st;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT_THREADS) void net_step_kernel(NetArgs<T> a) {
+  __shared__ bf16x8 sw[NT_FRAGS];                      // every layer's weight fragments
+  __shared__ bf16x8 sf[(NT_H + 10) * NT_PW];           // input features, tile + 5 halo
+  __shared__ __attribute__((aligned(16))) u16 sa[(NT_H + 8) * NT_PW * 32];  // layers 0, 2
+  __shared__ __attribute__((aligned(16))) u16 sb[(NT_H + 6) * NT_PW * 32];  // layers 1, 3
+  const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x % a.tiles_x;
+  const int y0 = ty * NT_H, x0 = tx * NT_W;
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+    for (int i = threadIdx.x; i < nt_frags(l); i += NT_THREADS)
+      sw[nt_frag_offset(l) + i] = a.w[l][i];
+  // features of rows y0 - 5 .. y0 + NT_H + 4, columns x0 - 5 .. x0 + NT_W + 4 (periodic)
+  for (int i = threadIdx.x; i < (NT_H + 10) * NT_PW; i += NT_THREADS) {
+    const int fr = i / NT_PW, fc = i % NT_PW;
+    const int y = wrap(y0 - 5 + fr, a.H), x = wrap(x0 - 5 + fc, a.W);
+    double m[4];
+    node_moments(a.f, a.phi, a.phib, a.plane, (long long)y * a.W + x, a.n_add, m);
+    sf[i] = features(a.F, make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]), y);
+  }
+  __syncthreads();
+  double ps[3] = {0.0, 0.0, 0.0};
+  nt_layer<true, 2, false>(a, sw + nt_frag_offset(0), sf, sa, 0, NT_H + 8, y0, x0, ps);
+  __syncthreads();
+  nt_layer<false, 2, false>(a, sw + nt_frag_offset(1), sa, sb, 1, NT_H + 6, y0, x0, ps);
+  __syncthreads();
+  nt_layer<false, 2, false>(a, sw + nt_frag_offset(2), sb, sa, 2, NT_H + 4, y0, x0, ps);
+  __syncthreads();
+  nt_layer<false, 2, false>(a, sw + nt_frag_offset(3), sa, sb, 3, NT_H + 2, y0, x0, ps);
+  __syncthreads();
+  nt_layer<false, 1, true>(a, sw + nt_frag_offset(4), sb, nullptr, 4, NT_H, y0, x0, ps);
+  if (a.proj) {  // uniform: every thread takes part in the fixed-order block sums
+    __shared__ double sh[NT_WAVES][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ps[k] += __shfl_xor(ps[k], d, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sh[wave][k] = ps[k];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double v = 0.0;
+      for (int w = 0; w < NT_WAVES; ++w) v += sh[w][threadIdx.x];
+      a.proj[3 * blockIdx.x + threadIdx.x] = v;
+    }
+  }
 }
 
 // full-weighting restriction by an even factor k, J-weighted along theta
@@ -858,7 +1033,6 @@ struct tlb_cnn {
   double* red;         // loss partials / statistics partials
   double* scalars;     // [8]: loss, statistics
   float* Jrow;
-  float* mbuf;         // moments of the grid being corrected [HW][4]
   double* proj;        // [H][3]
   int red_blocks;
   // graph of LEARN_GRAPH_CHUNK learned steps, bound to one grid's buffers and tile shape
@@ -1041,7 +1215,7 @@ void pair_launch(const tlb_grid* g, const tlb_grid* truth, float* m, float* y,
 // block per row), otherwise they are already in proj[nparts][3]
 template <typename T>
 void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* proj,
-                    int nparts, std::vector<tlbi_launch>& seq) {
+                    int nparts, bool rebase, std::vector<tlbi_launch>& seq) {
   if (nparts == 0) {
     ProjArgs pa{d, g->area, proj, g->p.n_phi, scale[0], scale[1]};
     seq.push_back(make_launch(reinterpret_cast<const void*>(&proj_kernel), dim3(g->p.n_theta),
@@ -1051,6 +1225,7 @@ void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* p
   ApplyArgs<T> aa{};
   aa.f = static_cast<T*>(g->f[0]);
   aa.phi = static_cast<T*>(g->phi[0]);
+  aa.phib = rebase ? reinterpret_cast<T*>(g->phi_base) : nullptr;
   aa.d = d;
   aa.partial = proj;
   aa.nparts = nparts;
@@ -1061,34 +1236,58 @@ void apply_launches(tlb_grid* g, const float* d, const float scale[4], double* p
                             dim3(blocks_for(aa.plane, 256)), dim3(256), aa));
 }
 
-// one learned step of grid g: three stage launches, moments, network, correction
+int net_tiles(int H, int W) { return ((H + NT_H - 1) / NT_H) * ((W + NT_W - 1) / NT_W); }
+
+// the network of a learned step of grid g (net_step_kernel): output in net->z, per-tile
+// area-weighted sums of the corrections (times scale[0], scale[1]) in net->proj
+template <typename T>
+tlbi_launch net_step_launch(const tlb_grid* g, const tlb_cnn* net, const float scale[4]) {
+  NetArgs<T> a{};
+  a.f = static_cast<const T*>(g->f[0]);
+  a.phi = static_cast<const T*>(g->phi[0]);
+  a.phib = reinterpret_cast<const T*>(g->phi_base);
+  a.plane = (long long)g->p.n_theta * g->p.n_phi;
+  a.n_add = stores_deviation<T>() ? g->n_ref : 0.0;
+  for (int l = 0; l < NL; ++l) {
+    a.w[l] = reinterpret_cast<const bf16x8*>(net->wf[l]);
+    a.bias[l] = bias_of(net, l);
+  }
+  a.F = make_features(net);
+  a.H = net->H;
+  a.W = net->W;
+  a.tiles_x = (net->W + NT_W - 1) / NT_W;
+  a.out = net->z;
+  a.proj = net->proj;
+  a.area = g->area;
+  a.s0 = scale[0];
+  a.s1 = scale[1];
+  return make_launch(reinterpret_cast<const void*>(&net_step_kernel<T>),
+                     dim3(net_tiles(net->H, net->W)), dim3(NT_THREADS), a);
+}
+
+// one learned step of grid g: three stage launches, the network, the correction
 void learned_step_seq(tlb_grid* g, tlb_cnn* net, std::vector<tlbi_launch>& seq) {
   for (int st = 1; st <= 3; ++st) {
     tlbi_launch l[2];
     const int n = tlbi_stage_launches(g, st, l);
     for (int i = 0; i < n; ++i) seq.push_back(l[i]);
   }
-  tlbi_launch rb;  // FP32: the order parameter's rebase after the step, as tlb_step_n does
-  if (tlbi_phi_rebase_launch(g, &rb)) seq.push_back(rb);
-  if (g->p.precision == 64)
-    pair_launch<double>(g, nullptr, net->mbuf, nullptr, seq);
-  else
-    pair_launch<float>(g, nullptr, net->mbuf, nullptr, seq);
   float scale[4];
   for (int c = 0; c < 4; ++c)
     scale[c] = (net->d.apply_mask == 0 || ((net->d.apply_mask >> c) & 1u)) ? net->d.out_scale[c] : 0.0f;
-  forward_seq(net, net->mbuf, nullptr, 1, seq);
-  // the last layer also forms the area-weighted sums of the corrections
-  ConvArgs* last = reinterpret_cast<ConvArgs*>(seq.back().args);
-  last->proj = net->proj;
-  last->area = g->area;
-  last->s0 = scale[0];
-  last->s1 = scale[1];
-  const int nparts = (int)seq.back().grid.x;
+  // moments, features and the five layers in one launch, which also forms the area-weighted
+  // sums of the corrections per tile
   if (g->p.precision == 64)
-    apply_launches<double>(g, net->z, scale, net->proj, nparts, seq);
+    seq.push_back(net_step_launch<double>(g, net, scale));
   else
-    apply_launches<float>(g, net->z, scale, net->proj, nparts, seq);
+    seq.push_back(net_step_launch<float>(g, net, scale));
+  const int nparts = (int)seq.back().grid.x;
+  // FP32: the correction also folds the order parameter into its base, so every learned step
+  // ends with a rebase
+  if (g->p.precision == 64)
+    apply_launches<double>(g, net->z, scale, net->proj, nparts, false, seq);
+  else
+    apply_launches<float>(g, net->z, scale, net->proj, nparts, true, seq);
 }
 
 void drop_learn_graph(tlb_cnn* net) {
@@ -1148,7 +1347,7 @@ bool graph_matches(const tlb_cnn* net, const tlb_grid* g) {
 
 void free_net(tlb_cnn* net) {
   void* bufs[] = {net->params, net->grad, net->mom, net->vel, net->z, net->e4, net->eA,
-                  net->eB, net->partial, net->red, net->scalars, net->Jrow, net->mbuf, net->proj};
+                  net->eB, net->partial, net->red, net->scalars, net->Jrow, net->proj};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int l = 0; l < NL; ++l) {
@@ -1222,8 +1421,10 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   alloc((void**)&net->red, (size_t)net->red_blocks * 8 * 8);
   alloc((void**)&net->scalars, 8 * 8);
   alloc((void**)&net->Jrow, net->H * 4);
-  alloc((void**)&net->mbuf, net->HW * 16);
-  alloc((void**)&net->proj, (size_t)(net->H > CONV_MAX_BLOCKS ? net->H : CONV_MAX_BLOCKS) * 3 * 8);
+  // partial sums of the corrections: one per row (tlb_apply_correction), per block of the
+  // output layer (forward), or per tile of the learned step's network
+  const size_t nproj = std::max<size_t>(std::max(net->H, CONV_MAX_BLOCKS), net_tiles(net->H, net->W));
+  alloc((void**)&net->proj, nproj * 3 * 8);
   if (e != hipSuccess) {
     free_net(net);
     return tlbi_fail(TLB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -1444,9 +1645,9 @@ int32_t tlb_apply_correction(tlb_grid* grid, const float* corrections) {
   const float one[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   std::vector<tlbi_launch> seq;
   if (grid->p.precision == 64)
-    apply_launches<double>(grid, corrections, one, grid->proj, 0, seq);
+    apply_launches<double>(grid, corrections, one, grid->proj, 0, false, seq);
   else
-    apply_launches<float>(grid, corrections, one, grid->proj, 0, seq);
+    apply_launches<float>(grid, corrections, one, grid->proj, 0, false, seq);
   return run_all(seq, grid->stream);
 }
 

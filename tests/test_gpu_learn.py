@@ -214,6 +214,50 @@ def test_learned_step_matches_reference(torch_cuda):
     assert ef <= 1e-2 * cf + 1e-14 and ep <= 1e-2 * cp + 1e-14
 
 
+@pytest.mark.parametrize("precision,shape", [(64, (16, 48)), (64, (13, 29)), (64, (5, 19)),
+                                               (64, (24, 72)), (32, (40, 100))])
+def test_learned_step_network_equals_layer_by_layer(torch_cuda, precision, shape):
+    """tlb_learned_step_n runs the network in one launch (8 x 24 tiles with a five-node halo,
+    activations in LDS); the public calls run it layer by layer (tlb_learn_pair,
+    tlb_cnn_forward, tlb_apply_correction).  Both make the same products in the same order
+    with the same bfloat16 roundings, so the network outputs agree bit for bit, and the states
+    after a step differ only by the summation order of the area-weighted mean correction
+    (rounding of the FP64 sums, FP64 grids) and by where the order parameter is folded into
+    its base (FP32 grids).  Shapes: several tiles with ragged edges, a grid smaller than one
+    tile in both directions (wrap-around halo), an exact multiple of the tile."""
+    torch = torch_cuda
+    from paper_1904_10070_amd import TorusGrid
+    from paper_1904_10070_amd.binding import learned_step, learn_pair, apply_correction
+    H, W = shape
+    p = inputs.TorusParams(1.0, 2.5, H, W, 0.5, 2e-3, 0.05, 0.3, 2e-4)
+    state = inputs.random_state(p, seed=31)
+    net = make_net(torch, H, W, 1, params_with_biases(32))
+    a, b = TorusGrid(p, precision), TorusGrid(p, precision)
+    for g in (a, b):
+        g.set_state(*state)
+    learned_step(a, net, 1)
+    b.step(1)
+    m, _ = learn_pair(b)
+    z = net.forward(m[None])
+    apply_correction(b, z[0].contiguous())   # tlb_cnn_forward returns z * out_scale
+    fa, pa = (x.cpu().numpy().astype(np.float64) for x in a.get_state())
+    fb, pb = (x.cpu().numpy().astype(np.float64) for x in b.get_state())
+    # the size of the correction: the step without it
+    c = TorusGrid(p, precision)
+    c.set_state(*state)
+    c.step(1)
+    f1, p1 = (x.cpu().numpy().astype(np.float64) for x in c.get_state())
+    cf, cp = np.abs(fb - f1).max(), np.abs(pb - p1).max()
+    ef, ep = np.abs(fa - fb).max(), np.abs(pa - pb).max()
+    print(f"{precision} {shape}: |df| {ef:.2e} of correction {cf:.2e}; |dphi| {ep:.2e} of {cp:.2e}",
+          flush=True)
+    assert cf > 0 and cp > 0
+    if precision == 64:
+        assert ef <= 1e-12 * cf and ep <= 1e-12 * cp
+    else:  # a few FP32 roundings of f (~0.1) and phi (~1)
+        assert ef <= 3e-8 and ep <= 3e-7
+
+
 def test_learned_step_graph_is_bitwise(torch_cuda):
     """40 learned steps as one 32-step graph replay plus 8 plain steps, against 40 plain."""
     torch = torch_cuda
