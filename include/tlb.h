@@ -240,7 +240,7 @@ int32_t tlb_autotune(tlb_grid* grid, int32_t* rows);
 
 /* Ensembles of tori (coarsening statistics over tori of different aspect ratios and grid
  * sizes, section IV): tlb_batch_step_n advances every grid of the batch by n_steps with one
- * persistent fused launch per Runge-Kutta stage covering the tiles of all grids (each grid
+ * fused launch per Runge-Kutta stage covering the tiles of all grids (each grid
  * keeps its own parameters, time step and buffers), replayed from graphs as tlb_step_n's.
  * Each grid ends exactly (bit for bit) where tlb_step_n on it alone would.  The batch
  * keeps pointers to the grids, which must outlive it and must not be stepped on their own

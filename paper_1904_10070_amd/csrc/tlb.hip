@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -908,32 +909,50 @@ __global__ __launch_bounds__(256) void tlb_ch4_prep_kernel(Ch4Args<T> a) {
   a.Q[x] = (nup * inv_n) * ph;
 }
 
-// One stage for an ensemble of grids in one persistent launch.  table[3 g + stage - 1] holds
-// the stage arguments of grid g; tile_begin[g] is the first tile of grid g in the concatenated
-// tile order (tile_begin[n] = total).  XCD x owns a contiguous range of that order, which its
-// gridDim.x / 8 resident blocks walk with a stride, tile by tile.
+// One stage for an ensemble of grids in one launch, one block per tile.  table[3 g + stage - 1]
+// holds the stage arguments of grid g; tile_begin[g] is the first tile of grid g in the
+// concatenated tile order (tile_begin[n] = total).  Blocks go round-robin to the 8 XCDs, and
+// XCD x takes a contiguous range of that order, so that each XCD's L2 serves whole grids, or
+// compact parts of them, as for a single grid.  (A persistent form, the resident blocks walking
+// the tiles, was 10-14 % slower: each tile's copies then queued behind the previous tile's
+// stores.)
+// A pointer read from device memory (the batch's argument table) is generic to the compiler,
+// which then accesses it with flat instructions; those also count against the LDS wait
+// counter, so every wait for an LDS read would wait for the global loads in flight too.  Cast
+// through the global address space, the pointer gets global (and scalar) instructions, as a
+// kernel argument does.
+template <typename P>
+__device__ __forceinline__ P* global_ptr(P* p) {
+  return (P*)((__attribute__((address_space(1))) P*)reinterpret_cast<uintptr_t>(p));
+}
+
 template <typename T, bool VEC, int TY, bool GENREF = false, bool STREAM = false>
 __global__ __launch_bounds__(Tile<TY>::NT) __attribute__((amdgpu_waves_per_eu(
     StageWaves<T>::value))) void tlb_stage_batch_kernel(
     const StageArgs<T>* __restrict__ table, const int* __restrict__ tile_begin, int n, int stage) {
   const int total = tile_begin[n];
-  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
   const int full = total >> 3, rem = total & 7;
-  const int t0 = xcd * full + min(xcd, rem), cnt = full + (xcd < rem ? 1 : 0);
-  for (int i = local; i < cnt; i += per) {
-    const int t = t0 + i;
-    int lo = 0, hi = n - 1;  // the grid owning tile t: the last g with tile_begin[g] <= t
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_begin[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const StageArgs<T> a = table[3 * lo + stage - 1];
-    int tx, ty;
-    band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
-    stage_tile<T, VEC, TY, false, STREAM, GENREF>(a, tx, ty);
-    __syncthreads();  // the next tile reuses the LDS tiles
+  if (local >= full + (xcd < rem ? 1 : 0)) return;
+  const int t = xcd * full + min(xcd, rem) + local;
+  int lo = 0, hi = n - 1;  // the grid owning tile t: the last g with tile_begin[g] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_begin[mid] <= t) lo = mid;
+    else hi = mid - 1;
   }
+  StageArgs<T> a = table[3 * lo + stage - 1];
+  a.fin = global_ptr(a.fin);
+  a.phin = global_ptr(a.phin);
+  a.f0 = global_ptr(a.f0);
+  a.phi0 = global_ptr(a.phi0);
+  a.fout = global_ptr(a.fout);
+  a.phiout = global_ptr(a.phiout);
+  a.rows = global_ptr(a.rows);
+  if (a.phib) a.phib = global_ptr(a.phib);
+  int tx, ty;
+  band_tile(t - tile_begin[lo], a.ntx, a.nty, tx, ty);
+  stage_tile<T, VEC, TY, false, STREAM, GENREF>(a, tx, ty);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1751,7 +1770,7 @@ void drop_batch_graph(tlb_batch* b) {
 }
 
 // (Re)build the argument table and the tile offsets of the batch for its tile height, and the
-// size of the persistent grid (blocks resident on the whole GPU at once, a multiple of 8).
+// launch size (one block per tile, rounded up to a multiple of the 8 XCDs).
 template <typename T>
 int32_t batch_setup_t(tlb_batch* b) {
   std::string err;
@@ -1770,6 +1789,11 @@ int32_t batch_setup_t(tlb_batch* b) {
     for (int st = 1; st <= 3; ++st) tab[3 * i + st - 1] = stage_args<T>(&tmp, st);
     tb[i] = (int)total;
     total += stage_blocks(&tmp);
+    if (total > (long long)INT_MAX - 8) {
+      std::free(tab);
+      std::free(tb);
+      return fail(TLB_EINVAL, "ensemble has too many tiles");
+    }
   }
   tb[b->n] = (int)total;
   b->total_tiles = (int)total;
@@ -1782,15 +1806,7 @@ int32_t batch_setup_t(tlb_batch* b) {
   std::free(tab);
   std::free(tb);
   if (e != hipSuccess) return fail(TLB_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
-  const void* fn = batch_fn<T>(b);
-  int dev = 0, cus = 0, per_cu = 0;
-  TLB_HIP_CHECK(hipGetDevice(&dev));
-  TLB_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  TLB_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TX * b->ty, 0));
-  const long long resident = (long long)cus * (per_cu > 0 ? per_cu : 1);
-  long long blocks = total < resident ? total : resident;
-  blocks = (blocks + 7) / 8 * 8;
-  b->blocks = (int)(blocks > 8 ? blocks : 8);
+  b->blocks = (int)((total + 7) / 8 * 8);  // one block per tile, a multiple of the 8 XCDs
   drop_batch_graph(b);
   return TLB_OK;
 }
