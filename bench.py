@@ -505,7 +505,7 @@ def main():
         out["fp32_graph_1s"] = leg_json(d)
         t_fine = d["t_step"]
         d = graph_leg(p, 64, seconds=1.0)
-        out["fp64"] = leg_json(d)
+        out["fp64"] = leg_json(d, traffic=measured_traffic("spinodal512x1280_fp64"))
         pr = inputs.roofline_workload()
         d = graph_leg(pr, 32, seconds=1.0)
         out["fp32_2048x5120"] = leg_json(
