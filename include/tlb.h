@@ -168,9 +168,11 @@ int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void
  * factors r and J (eq. boltz_tor); velocity-space force and connection terms through K^H
  * (section II C); Cahn-Hilliard right-hand side -div(u phi) + M Delta_S mu (eq. CH) --
  * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous (unless check_every
- * > 0, see tlb_params).  Unless TLB_NO_GRAPH, the steps are replayed from graphs of kernel
- * nodes: one of 32 steps for every full run of 32 and one of the remainder's length, each
- * built on first use and kept; the graphs keep the buffer pointers given at creation.
+ * > 0, see tlb_params).  The steps run in runs of at most 32 that end where the FP32 order
+ * parameter is folded into its base (every 32nd step since tlb_set_state; FP64 grids: every
+ * 32 steps of the call).  Unless TLB_NO_GRAPH, each run replays a graph of kernel nodes of
+ * its length, built on first use and kept; the graphs keep the buffer pointers given at
+ * creation.
  * Errors: TLB_EINVAL, TLB_EHIP (launch or graph failure), TLB_ENONFINITE (check_every > 0
  * and a check of this call found NaN or Inf).                                             */
 int32_t tlb_step_n(tlb_grid* grid, int64_t n_steps);
