@@ -272,15 +272,17 @@ struct WgradArgs {
 };
 
 // The global loads of one strip, all issued before any is used: the error tile (thread u <
-// (COS/8) 64 takes node u % 64, channels 8 (u / 64) .. + 7) and the nine shifted input tiles
-// (KA loads per thread, same mapping per tap), zero beyond the row's end for the error.
+// (COS/8) 64 takes node u % 64, channels 8 (u / 64) .. + 7) and the nine shifted input tiles,
+// by pairs of neighbouring nodes (unit u: nodes 2 (u % 32) and +1, channels 8 c8 .. + 7, so
+// that each LDS store of the transposed tile writes two consecutive nodes), KA units per
+// thread; the error is zero beyond the row's end.
 template <int CIS, int COS, bool MOM>
 struct WgradStrip {
   static constexpr int NE = (COS / 8) * 64;
-  static constexpr int NA = 9 * (CIS / 8) * 64;
+  static constexpr int NA = 9 * (CIS / 8) * 32;
   static constexpr int KA = (NA + WG_THREADS - 1) / WG_THREADS;
   uint4 e;
-  uint4 av[KA];  // bf16 inputs, or the float moments (MOM)
+  uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
 
   __device__ __forceinline__ void load(const WgradArgs& a, int s) {
     const int xb = s % a.xs;
@@ -298,19 +300,22 @@ struct WgradStrip {
     for (int k = 0; k < KA; ++k) {
       const int u = threadIdx.x + k * WG_THREADS;
       if (u < NA) {
-        const int j = u & 63;
-        const int r2 = u >> 6;
+        const int jp = u & 31;
+        const int r2 = u >> 5;
         const int c8 = r2 % (CIS / 8), t = r2 / (CIS / 8);
         const int yy = wrap(y + t / 3 - 1, a.H);
-        const int xx = wrap(x0 + j + t % 3 - 1, a.W);
-        if constexpr (MOM) {
-          const int smp = a.idx ? a.idx[n] : n;
-          const float4 m = static_cast<const float4*>(a.a)[((size_t)smp * a.H + yy) * a.W + xx];
-          av[k] = make_uint4(__float_as_uint(m.x), __float_as_uint(m.y), __float_as_uint(m.z),
-                             __float_as_uint(m.w));
-        } else {
-          av[k] = *reinterpret_cast<const uint4*>(
-              static_cast<const u16*>(a.a) + (((size_t)n * a.H + yy) * a.W + xx) * CIS + 8 * c8);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int xx = wrap(x0 + 2 * jp + h + t % 3 - 1, a.W);
+          if constexpr (MOM) {
+            const int smp = a.idx ? a.idx[n] : n;
+            const float4 m = static_cast<const float4*>(a.a)[((size_t)smp * a.H + yy) * a.W + xx];
+            av[k][h] = make_uint4(__float_as_uint(m.x), __float_as_uint(m.y),
+                                  __float_as_uint(m.z), __float_as_uint(m.w));
+          } else {
+            av[k][h] = *reinterpret_cast<const uint4*>(
+                static_cast<const u16*>(a.a) + (((size_t)n * a.H + yy) * a.W + xx) * CIS + 8 * c8);
+          }
         }
       }
     }
@@ -335,25 +340,30 @@ struct WgradStrip {
     for (int k = 0; k < KA; ++k) {
       const int u = threadIdx.x + k * WG_THREADS;
       if (u < NA) {
-        const int j = u & 63;
-        const int r2 = u >> 6;
+        const int jp = u & 31;
+        const int r2 = u >> 5;
         const int c8 = r2 % (CIS / 8), t = r2 / (CIS / 8);
-        u16 v[8];
-        if constexpr (MOM) {
-          const int yy = wrap(y + t / 3 - 1, a.H);
-          const float4 m = make_float4(__uint_as_float(av[k].x), __uint_as_float(av[k].y),
-                                       __uint_as_float(av[k].z), __uint_as_float(av[k].w));
-          float x[8];
-          features_f(a.F, m, yy, x);
+        u16 v[2][8];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) v[i] = to_bf16(x[i]);
-        } else {
-          const unsigned w4[4] = {av[k].x, av[k].y, av[k].z, av[k].w};
+        for (int h = 0; h < 2; ++h) {
+          if constexpr (MOM) {
+            const int yy = wrap(y + t / 3 - 1, a.H);
+            const float4 m = make_float4(__uint_as_float(av[k][h].x), __uint_as_float(av[k][h].y),
+                                         __uint_as_float(av[k][h].z), __uint_as_float(av[k][h].w));
+            float x[8];
+            features_f(a.F, m, yy, x);
 #pragma unroll
-          for (int i = 0; i < 8; ++i) v[i] = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
+            for (int i = 0; i < 8; ++i) v[h][i] = to_bf16(x[i]);
+          } else {
+            const unsigned w4[4] = {av[k][h].x, av[k][h].y, av[k][h].z, av[k][h].w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[h][i] = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) sA[(t * CIS + 8 * c8 + i) * WG_PITCH + j] = v[i];
+        for (int i = 0; i < 8; ++i)
+          *reinterpret_cast<unsigned*>(&sA[(t * CIS + 8 * c8 + i) * WG_PITCH + 2 * jp]) =
+              (unsigned)v[0][i] | ((unsigned)v[1][i] << 16);
       }
     }
   }
