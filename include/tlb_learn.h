@@ -78,8 +78,11 @@ typedef struct {
   int32_t step;
 } tlb_adam;
 
-/* Create a network with zero weights; load weights with tlb_cnn_set_params.  Errors:
- * TLB_EINVAL (sizes, radii, non-finite or zero scales), TLB_ENOMEM, TLB_EHIP.              */
+/* Create a network with zero weights; load weights with tlb_cnn_set_params.  The handle owns
+ * its device workspaces: bf16 activations, error signals and outputs of max_batch samples
+ * (416 B per node and sample), the weights, gradients and Adam moments, and 28 MB of
+ * per-workgroup partial gradients; freed by tlb_cnn_destroy.  Errors: TLB_EINVAL (sizes,
+ * radii, non-finite or zero scales), TLB_ENOMEM, TLB_EHIP.                                  */
 int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out);
 void tlb_cnn_destroy(tlb_cnn* net);
 
