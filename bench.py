@@ -419,7 +419,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1904_10070_amd import inputs, load_library, WENO5
+    from paper_1904_10070_amd import inputs, load_library, WENO5, CH4
     load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
@@ -518,6 +518,17 @@ def main():
         # the WENO-5 advection variant (nonlinear face weights: arithmetic-bound)
         d = graph_leg(p.with_(flags=WENO5), 32, seconds=0.5)
         out["weno5_fp32"] = leg_json(d, vs_uw5=d["nups"] / out["fp32_graph_1s"]["value"])
+        # the fourth-order Cahn-Hilliard variant: a prepass per stage (reads the 16 populations
+        # and phi, writes mu and the two advection fluxes) whose three planes the stage kernel
+        # reads as halo tiles: 136 + 3 x 23 = 205 values per node and step.  Its surface
+        # Laplacian has a larger spectral radius (the five-point fourth-order symbol reaches
+        # 16/3 against 4), so the time step is halved to stay inside the explicit bound.
+        d = graph_leg(p.with_(flags=CH4, dt=p.dt / 2), 32, seconds=0.5)
+        ch4_gbs = 205 * 4 * d["nups"] / 1e9
+        out["ch4_fp32"] = leg_json(d, vs_uw5=d["nups"] / out["fp32_graph_1s"]["value"],
+                                   values_per_node_step=205, achieved_gbs_with_prepass=ch4_gbs,
+                                   roofline_frac_with_prepass=ch4_gbs / HBM_PEAK_GBS,
+                                   dt=p.dt / 2, nonfinite=d["nonfinite"])
         out["ensemble64_fp32"] = ensemble_leg()
         out["learned_coarse_fp32"] = learned_leg(t_fine)
     if not args.no_cpu:

@@ -6,7 +6,7 @@ seeded synthetic initial conditions.
 """
 from . import inputs  # noqa: F401
 from .binding import (TorusGrid, TorusBatch, load_library, stable_dt, TlbError, FLAT,  # noqa: F401
-                      CH_NO_ADVECTION, NO_GRAPH, WENO5, STRICT_DT)
+                      CH_NO_ADVECTION, NO_GRAPH, WENO5, STRICT_DT, CH4)
 
 __all__ = ["TorusGrid", "TorusBatch", "load_library", "stable_dt", "TlbError", "FLAT",
-           "CH_NO_ADVECTION", "NO_GRAPH", "WENO5", "STRICT_DT", "inputs"]
+           "CH_NO_ADVECTION", "NO_GRAPH", "WENO5", "STRICT_DT", "CH4", "inputs"]
