@@ -170,9 +170,10 @@ int32_t tlb_set_state(tlb_grid* grid, const void* f, const void* phi, const void
  * combined by the SSP Runge-Kutta stages.  Stream-ordered, asynchronous (unless check_every
  * > 0, see tlb_params).  The steps run in runs of at most 32 that end where the FP32 order
  * parameter is folded into its base (every 32nd step since tlb_set_state; FP64 grids: every
- * 32 steps of the call).  Unless TLB_NO_GRAPH, each run replays a graph of kernel nodes of
- * its length, built on first use and kept; the graphs keep the buffer pointers given at
- * creation.
+ * 32 steps of the call).  Unless TLB_NO_GRAPH, each run replays graphs of kernel nodes of
+ * 32, 16, 8, 4, 2 and 1 steps (the binary digits of its length), all built together on the
+ * first call that needs one and kept, so that no later call builds a graph; the graphs keep
+ * the buffer pointers given at creation.
  * Errors: TLB_EINVAL, TLB_EHIP (launch or graph failure), TLB_ENONFINITE (check_every > 0
  * and a check of this call found NaN or Inf).                                             */
 int32_t tlb_step_n(tlb_grid* grid, int64_t n_steps);

@@ -1468,6 +1468,8 @@ int32_t build_learn_graph(tlb_grid* g, tlb_cnn* net) {
       prev = node;
     }
   if (e == hipSuccess) e = hipGraphInstantiate(&net->chunk_exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess && (e = hipGraphUpload(net->chunk_exec, g->stream)) != hipSuccess)
+    (void)hipGraphExecDestroy(net->chunk_exec);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     net->chunk_exec = nullptr;

@@ -1560,7 +1560,7 @@ constexpr int GRAPH_CHUNK = TLBI_GRAPH_CHUNK;
 // valid until the graph is instantiated
 template <class MakeParams>
 hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_params,
-                       int steps, hipGraphExec_t* out) {
+                       int steps, hipStream_t stream, hipGraphExec_t* out) {
   hipGraph_t graph;
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return e;
@@ -1579,6 +1579,8 @@ hipError_t build_chain(const void* fn, dim3 grid, dim3 block, MakeParams make_pa
       prev = node;
     }
   if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess && (e = hipGraphUpload(*out, stream)) != hipSuccess)
+    (void)hipGraphExecDestroy(*out);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) *out = nullptr;
   return e;
@@ -1619,11 +1621,27 @@ int32_t build_step_graph(tlb_grid* g, int steps, bool close) {
   if (e == hipSuccess && close && tlbi_phi_rebase_launch(g, &rb)) add(rb, &rbp);
   hipGraphExec_t& slot = g->graphs[close ? 1 : 0][steps];
   if (e == hipSuccess) e = hipGraphInstantiate(&slot, graph, nullptr, nullptr, 0);
+  // uploaded now, so that the first launch of the graph costs what every other launch costs
+  if (e == hipSuccess && (e = hipGraphUpload(slot, g->stream)) != hipSuccess)
+    (void)hipGraphExecDestroy(slot);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     slot = nullptr;
     return fail(TLB_EHIP, std::string("graph build: ") + hipGetErrorString(e));
   }
+  return TLB_OK;
+}
+
+// Every graph the step loop uses: runs of 1, 2, 4, .., GRAPH_CHUNK steps, and for FP32 grids
+// each also closed by the fold of the order parameter.
+template <typename T>
+int32_t build_step_graphs(tlb_grid* g) {
+  for (int c = 0; c < (g->phi_base ? 2 : 1); ++c)
+    for (int len = 1; len <= GRAPH_CHUNK; len <<= 1)
+      if (!g->graphs[c][len]) {
+        int32_t rc = build_step_graph<T>(g, len, c == 1);
+        if (rc != TLB_OK) return rc;
+      }
   return TLB_OK;
 }
 
@@ -1681,12 +1699,20 @@ int32_t step_n_t(tlb_grid* g, int64_t n) {
         if (rc != TLB_OK) return rc;
       }
     } else {
-      hipGraphExec_t& x = g->graphs[r.close ? 1 : 0][r.steps];
-      if (!x) {
-        int32_t rc = build_step_graph<T>(g, r.steps, r.close);
-        if (rc != TLB_OK) return rc;
+      // the run as graphs of 32, 16, 8, 4, 2 and 1 steps (its binary digits, largest first;
+      // the last one carries the fold), all built together on first use: no later call builds
+      // a graph, whatever its length and the fold phase it starts at
+      for (int left = r.steps; left > 0;) {
+        int piece = GRAPH_CHUNK;
+        while (piece > left) piece >>= 1;
+        left -= piece;
+        hipGraphExec_t& x = g->graphs[r.close && left == 0 ? 1 : 0][piece];
+        if (!x) {
+          int32_t rc = build_step_graphs<T>(g);
+          if (rc != TLB_OK) return rc;
+        }
+        TLB_HIP_CHECK(hipGraphLaunch(x, g->stream));
       }
-      TLB_HIP_CHECK(hipGraphLaunch(x, g->stream));
     }
     advance_phase(g, r.steps);
     done += r.steps;
@@ -1827,7 +1853,9 @@ int32_t batch_step_t(tlb_batch* b, int64_t n) {
   for (int64_t done = 0; done < n;) {
     int s = (int)std::min<int64_t>(GRAPH_CHUNK, n - done);  // up to the next rebase of any grid
     for (int i = 0; i < b->n; ++i) s = std::min(s, next_run(b->grids[i], s).steps);
-    if (!b->graphs[s]) {
+    bool missing = false;  // graphs of 1, 2, 4, .., GRAPH_CHUNK steps, all built on first use
+    for (int len = 1; len <= GRAPH_CHUNK; len <<= 1) missing = missing || !b->graphs[len];
+    if (missing) {
       const void* fn = batch_fn<T>(b);
       const StageArgs<T>* table = static_cast<const StageArgs<T>*>(b->table);
       const int* tile_begin = b->tile_begin;
@@ -1836,12 +1864,21 @@ int32_t batch_step_t(tlb_batch* b, int64_t n) {
       void* params[3][4] = {{&table, &tile_begin, &nn, &stages[0]},
                             {&table, &tile_begin, &nn, &stages[1]},
                             {&table, &tile_begin, &nn, &stages[2]}};
-      hipError_t e = build_chain(fn, dim3(b->blocks), dim3(TX * b->ty),
-                                 [&](int st) { return params[st - 1]; }, s, &b->graphs[s]);
-      if (e != hipSuccess)
-        return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
+      for (int len = 1; len <= GRAPH_CHUNK; len <<= 1) {
+        if (b->graphs[len]) continue;
+        hipError_t e = build_chain(fn, dim3(b->blocks), dim3(TX * b->ty),
+                                   [&](int st) { return params[st - 1]; }, len, b->stream,
+                                   &b->graphs[len]);
+        if (e != hipSuccess)
+          return fail(TLB_EHIP, std::string("batch graph build: ") + hipGetErrorString(e));
+      }
     }
-    TLB_HIP_CHECK(hipGraphLaunch(b->graphs[s], b->stream));
+    for (int left = s; left > 0;) {  // the run's binary digits, largest first
+      int piece = GRAPH_CHUNK;
+      while (piece > left) piece >>= 1;
+      left -= piece;
+      TLB_HIP_CHECK(hipGraphLaunch(b->graphs[piece], b->stream));
+    }
     for (int i = 0; i < b->n; ++i) {  // each grid rebases where it would when stepped alone
       tlb_grid* g = b->grids[i];
       const bool close = next_run(g, s).close;

@@ -27,9 +27,9 @@ struct tlb_grid {
   int red_blocks, rows_per_block;
   size_t elem;
   int ty;                     // tile height of the stage kernel (4, 8 or 16)
-  // graphs[c][s]: s = 1..TLBI_GRAPH_CHUNK time steps as one graph of kernel nodes, closed by the
-  // rebase of the order parameter when c = 1 (FP32), each built on the first call that needs it;
-  // graph_version: the grid's version when they were built
+  // graphs[c][s]: s = 1, 2, 4, .., TLBI_GRAPH_CHUNK time steps as one graph of kernel nodes,
+  // closed by the rebase of the order parameter when c = 1 (FP32), all built on the first call
+  // that needs one; graph_version: the grid's version when they were built
   hipGraphExec_t graphs[2][TLBI_GRAPH_CHUNK + 1];
   unsigned graph_version;
   void* dft_work;  // structure-factor workspace (built on first use): row transforms and twiddles
