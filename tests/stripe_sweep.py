@@ -128,10 +128,16 @@ def main(argv):
     prec = int(argv[1]) if len(argv) > 1 else 64
     t_end = float(argv[2]) if len(argv) > 2 else 800.0
     if len(argv) > 3 and argv[3] == "ch4":
-        # the second- against the fourth-order Cahn-Hilliard discretisation on the r = 0.8,
-        # N_theta = 320 torus (nu sweep at kappa = 5e-4)
-        cfgs = [(c, p.with_(flags=fl)) for fl in (0, CH4)
-                for c, p in configs(geometries=((0.8, 320),), kappas=())]
+        # the second- against the fourth-order Cahn-Hilliard discretisation on the r = 0.8
+        # torus, N_theta = 320 unless given (nu sweep at kappa = 5e-4)
+        nt = int(argv[4]) if len(argv) > 4 else 320
+        # finer grids: the time step scaled with the square of the spacing (the explicit
+        # Cahn-Hilliard bound; the fourth-order operator's spectrum is larger) and the two ends
+        # of the viscosity range
+        scale = (320.0 / nt) ** 2 if nt > 320 else 1.0
+        nus = NU_SET if nt <= 320 else (NU_SET[0], NU_SET[-1])
+        cfgs = [(c, p.with_(flags=fl, dt=p.dt * scale)) for fl in (0, CH4)
+                for c, p in configs(geometries=((0.8, nt),), nus=nus, kappas=())]
     else:
         cfgs = configs()
     rows = run(cfgs, prec, t_end, progress=lambda t: print(f"  t = {t:.0f}", flush=True))
