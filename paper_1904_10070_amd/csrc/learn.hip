@@ -10,13 +10,16 @@
 //                             channels; weights are staged once per workgroup in LDS in
 //                             fragment order (each lane reads its 16 bytes); the node
 //                             operand is one 16-byte load per lane and tap straight from the
-//                             channel-last activation tensor.  The input gradient is the same
+//                             channel-last activation tensor, the next tile's in flight
+//                             during a tile's products.  The input gradient is the same
 //                             kernel with the weights transposed and the taps mirrored.
 //   weight gradient           one workgroup = strips of 64 nodes of a row; the error signal
 //                             and the nine shifted input tiles are transposed into LDS so that
 //                             the contraction over nodes reads 8 consecutive nodes per lane;
 //                             the next strip's loads are in flight during a strip's products;
 //                             per-workgroup partial sums are added in a fixed order (FP64).
+// Grids are sized at network creation from the occupancy of each kernel: one wave of resident
+// workgroups where the per-workgroup set-up is large (weight gradient, 32-channel inputs).
 // Activations are bfloat16, channel-last [sample][theta][phi][channel].
 
 #include <hip/hip_runtime.h>
@@ -80,6 +83,12 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// periodic index for i in [-n, 2n): one conditional add or subtract, no division
+__device__ __forceinline__ int wrap1(int i, int n) {
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
+
 // The eight input features of a node from its raw moments (phi, n, u_theta, u_phi).
 struct Features {
   float shift[4], scale[4];
@@ -132,26 +141,59 @@ struct ConvArgs {
 constexpr int CONV_THREADS = 256;
 constexpr int CONV_WAVES = CONV_THREADS / 64;
 
+// A tile index t = (n H + y) xt + xb as its coordinates, advanced by a fixed stride with one
+// carry per coordinate instead of divisions (the stride's own coordinates are below xt and H).
+struct TileCursor {
+  int xb, y, n;
+  __device__ __forceinline__ void set(int t, int xt, int H) {
+    xb = t % xt;
+    const int rest = t / xt;
+    y = rest % H;
+    n = rest / H;
+  }
+  __device__ __forceinline__ void advance(const TileCursor& step, int xt, int H) {
+    xb += step.xb;
+    y += step.y;
+    n += step.n;
+    if (xb >= xt) {
+      xb -= xt;
+      ++y;
+    }
+    if (y >= H) {
+      y -= H;
+      ++n;
+    }
+  }
+};
+
 // The node operand of one tile: for each 32-long chunk c, this lane's 8 products -- tap c
 // with channels 8g..8g+7 (32-channel input), or tap 4c+g with all 8 channels (8-channel
 // input; taps 9..11 are zero padding).
 template <int IN, int KC>
-__device__ __forceinline__ void load_node_operand(const ConvArgs& a, int t, int px, int g,
-                                                  bf16x8 (&bf)[KC]) {
-  const int xb = t % a.xt;
-  const int rest = t / a.xt;
-  const int y = rest % a.H, n = rest / a.H;
-  const int x = xb * 16 + px;
+__device__ __forceinline__ void load_node_operand(const ConvArgs& a, const TileCursor& tc,
+                                                  int px, int g, bf16x8 (&bf)[KC]) {
+  const int y = tc.y, n = tc.n;
+  const int x = tc.xb * 16 + px;
+  // the rows and columns of the three offsets (y and x < W are in range, so one wrap is
+  // exact); nodes past the row's end, whose outputs are not stored, read its last node
+  int rows[3], cols[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rows[d] = wrap1(y + d - 1, a.H);
+    cols[d] = min(wrap1(x + d - 1, a.W), a.W - 1);
+  }
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     const int tap = IN == IN_BF32 ? c : 4 * c + g;
     bf[c] = zero_frag();
     if (tap < 9) {
-      const int yy = wrap(y + tap / 3 - 1, a.H);
-      const int xx = wrap(x + tap % 3 - 1, a.W);
-      const size_t pix = ((size_t)n * a.H + yy) * a.W + xx;
+      const int dy = tap / 3, dx = tap % 3;
+      const int yy = dy == 0 ? rows[0] : dy == 1 ? rows[1] : rows[2];
+      const int xx = dx == 0 ? cols[0] : dx == 1 ? cols[1] : cols[2];
+      // bf16 activations: n H W < 2^28 nodes, checked when the network is created
+      const int pix = (n * a.H + yy) * a.W + xx;
       if constexpr (IN == IN_BF32) {
-        bf[c] = static_cast<const bf16x8*>(a.in)[pix * 4 + g];
+        bf[c] = static_cast<const bf16x8*>(a.in)[(size_t)pix * 4 + g];
       } else if constexpr (IN == IN_BF8) {
         bf[c] = static_cast<const bf16x8*>(a.in)[pix];
       } else {
@@ -163,25 +205,59 @@ __device__ __forceinline__ void load_node_operand(const ConvArgs& a, int t, int 
   }
 }
 
+// The ReLU mask of a tile's outputs in this lane: node xb 16 + px (the row's last node for
+// lanes past its end, which store nothing), channels 16 b + 4 g .. + 3.
+template <int COB>
+__device__ __forceinline__ void load_tile_mask(const ConvArgs& a, const TileCursor& tc, int px,
+                                               int g, uint2 (&mk)[COB]) {
+  const size_t opix = ((size_t)tc.n * a.H + tc.y) * a.W + min(tc.xb * 16 + px, a.W - 1);
+#pragma unroll
+  for (int b = 0; b < COB; ++b)
+    mk[b] = *reinterpret_cast<const uint2*>(a.mask + opix * 32 + 16 * b + 4 * g);
+}
+
 template <int IN, int COB, int EPI>
 __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
   constexpr int KC = IN == IN_BF32 ? 9 : 3;  // 32-long product chunks
   __shared__ bf16x8 sw[KC * COB * 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // tiles are per wave
   const int px = lane & 15, g = lane >> 4;
   const int stride = gridDim.x * CONV_WAVES;
   int t = blockIdx.x * CONV_WAVES + wave;
+  TileCursor cur, step;
+  cur.set(t, a.xt, a.H);
+  step.set(stride, a.xt, a.H);
   // the first tile's node operand is in flight while the weights are staged
   bf16x8 bf[KC];
-  if (t < a.tiles) load_node_operand<IN, KC>(a, t, px, g, bf);
+  uint2 mk[COB];  // EPI_MASK: the ReLU mask, loaded with the tile's operand
+  if (t < a.tiles) {
+    load_node_operand<IN, KC>(a, cur, px, g, bf);
+    if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, cur, px, g, mk);
+  }
   for (int i = threadIdx.x; i < KC * COB * 64; i += CONV_THREADS) sw[i] = a.w[i];
+  // this lane's biases (output channels 16 b + 4 g + i; the output layer's four in lanes
+  // g = 0), held in registers: read per tile they would come after the tile's stores, and
+  // waiting for them would wait for the next tile's operand loads too
+  float bias[COB][4];
+#pragma unroll
+  for (int b = 0; b < COB; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      bias[b][i] = EPI == EPI_RELU ? a.bias[16 * b + 4 * g + i] : EPI == EPI_OUT ? a.bias[i] : 0.f;
   __syncthreads();
   double ps0 = 0.0, ps1 = 0.0, pa = 0.0;  // EPI_OUT projection sums of this lane
   for (; t < a.tiles; t += stride) {
-    const int xb = t % a.xt;
-    const int rest = t / a.xt;
-    const int y = rest % a.H, n = rest / a.H;
-    const int x = xb * 16 + px;
+    const int y = cur.y, n = cur.n;
+    const int x = cur.xb * 16 + px;
+    const bool live = x < a.W;
+    // lane holds node x, output channels 16 b + 4 g + i
+    const size_t opix = ((size_t)n * a.H + y) * a.W + x;
+    // the row area is loaded before the next tile's operands, which then stay in flight
+    // while the epilogue waits for it
+    double ar = 0.0;
+    if constexpr (EPI == EPI_OUT)
+      if (a.proj) ar = a.area[y];
     f32x4 acc[COB];
 #pragma unroll
     for (int b = 0; b < COB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -191,20 +267,27 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
       for (int b = 0; b < COB; ++b)
         acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sw[(c * COB + b) * 64 + lane], bf[c],
                                                          acc[b], 0, 0, 0);
-    if (t + stride < a.tiles) load_node_operand<IN, KC>(a, t + stride, px, g, bf);
-    if (x >= a.W) continue;
-    // lane holds node x, output channels 16 b + 4 g + i
-    const size_t opix = ((size_t)n * a.H + y) * a.W + x;
+    // the next tile's operand and mask (this tile's again after the last: unused, but
+    // loading them unconditionally keeps the epilogue's wait from covering these loads)
+    uint2 mcur[COB];  // this tile's mask, kept before the next one's is loaded
+    if constexpr (EPI == EPI_MASK)
+#pragma unroll
+      for (int b = 0; b < COB; ++b) mcur[b] = mk[b];
+    TileCursor next = cur;
+    if (t + stride < a.tiles) next.advance(step, a.xt, a.H);
+    load_node_operand<IN, KC>(a, next, px, g, bf);
+    if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, next, px, g, mk);
+    cur = next;
+    if (!live) continue;
     if constexpr (EPI == EPI_OUT) {
       if (g == 0) {
         float4 o;
-        o.x = acc[0][0] + a.bias[0];
-        o.y = acc[0][1] + a.bias[1];
-        o.z = acc[0][2] + a.bias[2];
-        o.w = acc[0][3] + a.bias[3];
+        o.x = acc[0][0] + bias[0][0];
+        o.y = acc[0][1] + bias[0][1];
+        o.z = acc[0][2] + bias[0][2];
+        o.w = acc[0][3] + bias[0][3];
         static_cast<float4*>(a.out)[opix] = o;
         if (a.proj) {
-          const double ar = a.area[y];
           ps0 += ar * (double)(o.x * a.s0);
           ps1 += ar * (double)(o.y * a.s1);
           pa += ar;
@@ -217,11 +300,10 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
         float v[4];
         if constexpr (EPI == EPI_RELU) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[b][i] + a.bias[co + i], 0.0f);
+          for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[b][i] + bias[b][i], 0.0f);
         } else {
-          const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + opix * 32 + co);
-          const u16 m4[4] = {(u16)(mk.x & 0xFFFF), (u16)(mk.x >> 16), (u16)(mk.y & 0xFFFF),
-                             (u16)(mk.y >> 16)};
+          const u16 m4[4] = {(u16)(mcur[b].x & 0xFFFF), (u16)(mcur[b].x >> 16),
+                             (u16)(mcur[b].y & 0xFFFF), (u16)(mcur[b].y >> 16)};
 #pragma unroll
           for (int i = 0; i < 4; ++i) v[i] = from_bf16(m4[i]) > 0.0f ? acc[b][i] : 0.0f;
         }
@@ -260,6 +342,8 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
 // weight gradient: dW[o][t][i] = sum over nodes of e[node][o] a[node + offset(t)][i]
 
 constexpr int WG_PITCH = 72;  // LDS row pitch (bf16): 64 nodes + 8 keeps rows 16-byte aligned
+// bf16 index of node j of row r
+__device__ __forceinline__ int wg_at(int r, int j) { return r * WG_PITCH + j; }
 constexpr int WG_THREADS = 256;
 
 struct WgradArgs {
@@ -271,50 +355,94 @@ struct WgradArgs {
   int n, H, W, xs, strips;  // xs = ceil(W / 64) strips per row; strips = n H xs
 };
 
+// A strip s = (n H + y) xs + xb (64 nodes of one row) as its coordinates; the strips of a
+// workgroup are consecutive, so the next one is one carry away.
+struct StripPos {
+  int xb, y, n;
+  __device__ __forceinline__ void set(int s, int xs, int H) {
+    xb = s % xs;
+    const int rest = s / xs;
+    y = rest % H;
+    n = rest / H;
+  }
+  __device__ __forceinline__ void next(int xs, int H) {
+    if (++xb == xs) {
+      xb = 0;
+      if (++y == H) {
+        y = 0;
+        ++n;
+      }
+    }
+  }
+};
+
 // The global loads of one strip, all issued before any is used: the error tile (thread u <
 // (COS/8) 64 takes node u % 64, channels 8 (u / 64) .. + 7) and the nine shifted input tiles,
-// by pairs of neighbouring nodes (unit u: nodes 2 (u % 32) and +1, channels 8 c8 .. + 7, so
-// that each LDS store of the transposed tile writes two consecutive nodes), KA units per
-// thread; the error is zero beyond the row's end.
+// by pairs of neighbouring nodes (unit u: nodes 2 (u % 32) and +1, channels 8 c8 .. + 7 with
+// c8 = (u / 32) % (CIS / 8), tap (u / 32) / (CIS / 8), so that each LDS store of the
+// transposed tile writes two consecutive nodes), KA units per thread; the error is zero
+// beyond the row's end.  With CIS / 8 even, the 64 units of a wavefront share their tap:
+// the taps are then found once per thread, from the wavefront index, and are scalars.
 template <int CIS, int COS, bool MOM>
 struct WgradStrip {
   static constexpr int NE = (COS / 8) * 64;
   static constexpr int NA = 9 * (CIS / 8) * 32;
   static constexpr int KA = (NA + WG_THREADS - 1) / WG_THREADS;
+  static constexpr bool UNIFORM = (CIS / 8) % 2 == 0;
   uint4 e;
   uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
+  int tap[KA];      // UNIFORM: tap of unit k, 9 where the thread has no unit k
 
-  __device__ __forceinline__ void load(const WgradArgs& a, int s) {
-    const int xb = s % a.xs;
-    const int rest = s / a.xs;
-    const int y = rest % a.H, n = rest / a.H;
-    const int x0 = xb * 64;
+  __device__ __forceinline__ void init(int wave) {
+    if constexpr (UNIFORM) {
+#pragma unroll
+      for (int k = 0; k < KA; ++k) {
+        // (u / 32) / (CIS / 8) with u / 32 = 2 wave + lane / 32 + 8 k: the lane's bit drops
+        const int t = (wave + 4 * k) / (CIS / 16);
+        tap[k] = t < 9 ? t : 9;
+      }
+    }
+  }
+  __device__ __forceinline__ int tap_of(int k) const {
+    if constexpr (UNIFORM) return tap[k];
+    const int u = threadIdx.x + k * WG_THREADS;
+    return u < NA ? (u >> 5) / (CIS / 8) : 9;
+  }
+
+  __device__ __forceinline__ void load(const WgradArgs& a, const StripPos& p) {
+    const int y = p.y, n = p.n;
+    const int x0 = p.xb * 64;
+    const int jp = threadIdx.x & 31;
     e = make_uint4(0, 0, 0, 0);
+    // bf16 tensors: n H W < 2^28 nodes, checked when the network is created; each load takes
+    // its row's start (uniform) and a 32-bit byte offset within the row
     if (threadIdx.x < NE) {
       const int j = threadIdx.x & 63, c8 = threadIdx.x >> 6;
+      const char* erow =
+          reinterpret_cast<const char*>(a.e) + (size_t)((n * a.H + y) * a.W) * COS * 2;
       if (x0 + j < a.W)
-        e = *reinterpret_cast<const uint4*>(a.e + (((size_t)n * a.H + y) * a.W + x0 + j) * COS +
-                                            8 * c8);
+        e = *reinterpret_cast<const uint4*>(erow + (unsigned)(((x0 + j) * COS + 8 * c8) * 2));
     }
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-      const int u = threadIdx.x + k * WG_THREADS;
-      if (u < NA) {
-        const int jp = u & 31;
-        const int r2 = u >> 5;
-        const int c8 = r2 % (CIS / 8), t = r2 / (CIS / 8);
-        const int yy = wrap(y + t / 3 - 1, a.H);
+      const int t = tap_of(k);
+      if (t < 9) {
+        const int c8 = ((threadIdx.x + k * WG_THREADS) >> 5) % (CIS / 8);
+        const int yy = wrap1(y + t / 3 - 1, a.H);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int xx = wrap(x0 + 2 * jp + h + t % 3 - 1, a.W);
+          // one wrap is exact for the row's nodes (x0 + 2 jp + h < W); those past its end,
+          // whose error is zero, read the row's last node
+          const int xx = min(wrap1(x0 + 2 * jp + h + t % 3 - 1, a.W), a.W - 1);
           if constexpr (MOM) {
             const int smp = a.idx ? a.idx[n] : n;
             const float4 m = static_cast<const float4*>(a.a)[((size_t)smp * a.H + yy) * a.W + xx];
             av[k][h] = make_uint4(__float_as_uint(m.x), __float_as_uint(m.y),
                                   __float_as_uint(m.z), __float_as_uint(m.w));
           } else {
-            av[k][h] = *reinterpret_cast<const uint4*>(
-                static_cast<const u16*>(a.a) + (((size_t)n * a.H + yy) * a.W + xx) * CIS + 8 * c8);
+            const char* arow =
+                static_cast<const char*>(a.a) + (size_t)((n * a.H + yy) * a.W) * CIS * 2;
+            av[k][h] = *reinterpret_cast<const uint4*>(arow + (unsigned)((xx * CIS + 8 * c8) * 2));
           }
         }
       }
@@ -323,7 +451,7 @@ struct WgradStrip {
 
   // transposed into LDS: sE[o][j] = e[n][y][x0 + j][o], sA[t][i][j] = a[n][y+dy][x0+j+dx][i];
   // bsum[i] accumulates this thread's error values (channel 8 (tid / 64) + i)
-  __device__ __forceinline__ void store(const WgradArgs& a, int s, u16* sE, u16* sA,
+  __device__ __forceinline__ void store(const WgradArgs& a, const StripPos& p, u16* sE, u16* sA,
                                         float (&bsum)[8]) const {
     if (threadIdx.x < NE) {
       const int j = threadIdx.x & 63, c8 = threadIdx.x >> 6;
@@ -331,39 +459,45 @@ struct WgradStrip {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const u16 v = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
-        sE[(8 * c8 + i) * WG_PITCH + j] = v;
+        sE[wg_at(8 * c8 + i, j)] = v;
         bsum[i] += from_bf16(v);
       }
     }
-    const int y = (s / a.xs) % a.H;
+    const int jp = threadIdx.x & 31;
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-      const int u = threadIdx.x + k * WG_THREADS;
-      if (u < NA) {
-        const int jp = u & 31;
-        const int r2 = u >> 5;
-        const int c8 = r2 % (CIS / 8), t = r2 / (CIS / 8);
-        u16 v[2][8];
+      const int t = tap_of(k);
+      if (t < 9) {
+        const int c8 = ((threadIdx.x + k * WG_THREADS) >> 5) % (CIS / 8);
+        unsigned w[2][4];  // the two nodes' channels 8 c8 .. + 7, two bf16 per word
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           if constexpr (MOM) {
-            const int yy = wrap(y + t / 3 - 1, a.H);
+            const int yy = wrap1(p.y + t / 3 - 1, a.H);
             const float4 m = make_float4(__uint_as_float(av[k][h].x), __uint_as_float(av[k][h].y),
                                          __uint_as_float(av[k][h].z), __uint_as_float(av[k][h].w));
             float x[8];
             features_f(a.F, m, yy, x);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[h][i] = to_bf16(x[i]);
+            for (int i = 0; i < 4; ++i)
+              w[h][i] = (unsigned)to_bf16(x[2 * i]) | ((unsigned)to_bf16(x[2 * i + 1]) << 16);
           } else {
-            const unsigned w4[4] = {av[k][h].x, av[k][h].y, av[k][h].z, av[k][h].w};
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[h][i] = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
+            w[h][0] = av[k][h].x;
+            w[h][1] = av[k][h].y;
+            w[h][2] = av[k][h].z;
+            w[h][3] = av[k][h].w;
           }
         }
+        // channel 2 i: the low halves of the two nodes' word i; channel 2 i + 1: the high
+        // halves (byte selectors 0-3 take the second operand's bytes, 4-7 the first's)
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          *reinterpret_cast<unsigned*>(&sA[(t * CIS + 8 * c8 + i) * WG_PITCH + 2 * jp]) =
-              (unsigned)v[0][i] | ((unsigned)v[1][i] << 16);
+        for (int i = 0; i < 4; ++i) {
+          // rows 2 i and 2 i + 1 of the group share their chunk order
+          unsigned* row =
+              reinterpret_cast<unsigned*>(sA + wg_at(t * CIS + 8 * c8 + 2 * i, 2 * jp));
+          row[0] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x05040100u);
+          row[WG_PITCH / 2] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x07060302u);
+        }
       }
     }
   }
@@ -377,7 +511,8 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   using Strip = WgradStrip<CIS, COS, MOM>;
   __shared__ __attribute__((aligned(16))) u16 sE[COS * WG_PITCH];
   __shared__ __attribute__((aligned(16))) u16 sA[9 * CIS * WG_PITCH];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 3;
   const int px = lane & 15, g = lane >> 4;
   f32x4 acc[FPW];
 #pragma unroll
@@ -385,13 +520,7 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int s0 = (int)((long long)blockIdx.x * a.strips / gridDim.x);
   const int s1 = (int)((long long)(blockIdx.x + 1) * a.strips / gridDim.x);
-  Strip st;
-  if (s0 < s1) st.load(a, s0);
-  for (int s = s0; s < s1; ++s) {
-    st.store(a, s, sE, sA, bsum);
-    // the next strip's loads are in flight during this strip's products
-    if (s + 1 < s1) st.load(a, s + 1);
-    __syncthreads();
+  auto products = [&]() {
 #pragma unroll
     for (int k = 0; k < FPW; ++k) {
       const int f = wave + 4 * k;
@@ -401,15 +530,30 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) {
           const bf16x8 A = co < COS ? *reinterpret_cast<const bf16x8*>(
-                                          &sE[co * WG_PITCH + 32 * kc + 8 * g])
+                                          &sE[wg_at(co, 32 * kc + 8 * g)])
                                     : zero_frag();
           const bf16x8 B = ci < CIS ? *reinterpret_cast<const bf16x8*>(
-                                          &sA[(t * CIS + ci) * WG_PITCH + 32 * kc + 8 * g])
+                                          &sA[wg_at(t * CIS + ci, 32 * kc + 8 * g)])
                                     : zero_frag();
           acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[k], 0, 0, 0);
         }
       }
     }
+  };
+  Strip st;
+  st.init(wave);
+  StripPos pos, nxt;
+  pos.set(s0, a.xs, a.H);
+  if (s0 < s1) st.load(a, pos);
+  for (int s = s0; s < s1; ++s) {
+    st.store(a, pos, sE, sA, bsum);
+    // the next strip's loads are in flight during this strip's products
+    nxt = pos;
+    nxt.next(a.xs, a.H);
+    if (s + 1 < s1) st.load(a, nxt);
+    pos = nxt;
+    __syncthreads();
+    products();
     __syncthreads();
   }
   float* out = a.partial + (size_t)blockIdx.x * (COS * 9 * CIS + COS);
@@ -1097,11 +1241,9 @@ __global__ __launch_bounds__(RED) void stats_kernel(StatArgs a) {
 // ------------------------------------------------------------------------------------------
 // host side
 
-// workgroups of a weight-gradient launch, each writing one partial gradient of the layer:
-// three per compute unit (164 VGPRs, 46 KB of LDS each), so that one workgroup's loads overlap
-// another's products (256, 512 and 768 measured 0.90, 0.75 and 0.73 ms per training step)
+// most workgroups of a weight-gradient launch (each writes one partial gradient of the layer)
 #ifndef TLB_WG_BLOCKS
-#define TLB_WG_BLOCKS 768
+#define TLB_WG_BLOCKS 2048
 #endif
 constexpr int WG_MAX_BLOCKS = TLB_WG_BLOCKS;
 constexpr int CONV_MAX_BLOCKS = 4096;
@@ -1182,6 +1324,8 @@ struct tlb_cnn {
   float* Jrow;
   double* proj;        // [H][3]
   int red_blocks;
+  int conv_grid[5];    // most workgroups of each convolution variant (conv_variant)
+  int wgrad_grid[NL];  // workgroups of each layer's weight-gradient launch
   // graph of LEARN_GRAPH_CHUNK learned steps, bound to one grid's buffers and tile shape
   hipGraphExec_t chunk_exec;
   unsigned long long chunk_grid;  // uid of the grid the graph was built for (0: none)
@@ -1213,6 +1357,14 @@ Features make_features(const tlb_cnn* net) {
   return F;
 }
 
+// index of a convolution variant: 0 moments input, 1 8-channel input, 2-4 32-channel input
+// with the output layer's, the ReLU-mask and the bias + ReLU epilogue
+int conv_variant(int in, int epi) {
+  if (in == IN_MOM) return 0;
+  if (in == IN_BF8) return 1;
+  return epi == EPI_OUT ? 2 : epi == EPI_MASK ? 3 : 4;
+}
+
 const void* conv_fn(int in, int cob, int epi) {
   if (in == IN_MOM) return reinterpret_cast<const void*>(&conv_kernel<IN_MOM, 2, EPI_RELU>);
   if (in == IN_BF8) return reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_MASK>);
@@ -1239,7 +1391,8 @@ tlbi_launch conv_launch(const tlb_cnn* net, int in, int cob, int epi, const void
   a.xt = (net->W + 15) / 16;
   a.tiles = n * net->H * a.xt;
   int blocks = blocks_for(a.tiles, CONV_WAVES);
-  if (blocks > CONV_MAX_BLOCKS) blocks = CONV_MAX_BLOCKS;
+  const int cap = net->conv_grid[conv_variant(in, epi)];
+  if (blocks > cap) blocks = cap;
   return make_launch(conv_fn(in, cob, epi), dim3(blocks), dim3(CONV_THREADS), a);
 }
 
@@ -1299,7 +1452,7 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
     wa.W = net->W;
     wa.xs = (net->W + 63) / 64;
     wa.strips = n * net->H * wa.xs;
-    const int wblocks = wa.strips < WG_MAX_BLOCKS ? wa.strips : WG_MAX_BLOCKS;
+    const int wblocks = std::min(wa.strips, net->wgrad_grid[l]);
     seq.push_back(make_launch(wgrad_fn(l), dim3(wblocks), dim3(WG_THREADS), wa));
     GradArgs ga{net->partial, net->grad + layer_offset(l), wblocks, L_CIS[l], L_COS[l], L_CIN[l],
                 L_COUT[l], scale};
@@ -1549,7 +1702,39 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   const size_t P = TLB_CNN_PARAMS;
   net->red_blocks = blocks_for((long long)nb, RED);
   if (net->red_blocks < 1024) net->red_blocks = 1024;
-  hipError_t e = hipSuccess;
+  // Convolution grids.  A 32-channel-input workgroup stages 18 KB of weight fragments in LDS
+  // before its first tile: those kernels run one wave of resident workgroups, each wavefront
+  // then taking many tiles with the next tile's loads in flight (measured on 16 x 128 x 320:
+  // 0.72-0.78x the time of 4096 workgroups).  The others stage 6 KB and balance better with
+  // up to 4096 workgroups.
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (int v = 0; v < 5 && e == hipSuccess; ++v) {
+    net->conv_grid[v] = CONV_MAX_BLOCKS;
+    if (v < 2) continue;
+    int resident = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &resident, conv_fn(IN_BF32, v == 2 ? 1 : 2, v == 2 ? EPI_OUT : v == 3 ? EPI_MASK : EPI_RELU),
+        CONV_THREADS, 0);
+    if (e == hipSuccess)
+      net->conv_grid[v] = (int)std::min<long long>(CONV_MAX_BLOCKS,
+                                                   (long long)std::max(resident, 1) * cus);
+  }
+  // Weight-gradient grids: one wave of resident workgroups (LDS or registers limit them to
+  // 3 to 5 per compute unit), each taking consecutive strips, the next strip's loads in
+  // flight during a strip's products.
+  for (int l = 0; l < NL && e == hipSuccess; ++l) {
+    int resident = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, wgrad_fn(l), WG_THREADS, 0);
+    if (e == hipSuccess)
+      net->wgrad_grid[l] =
+          (int)std::min<long long>(WG_MAX_BLOCKS, (long long)std::max(resident, 1) * cus);
+  }
+  if (e != hipSuccess) {
+    free_net(net);
+    return tlbi_fail(TLB_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+  }
   auto alloc = [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
   };
@@ -1566,7 +1751,10 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   alloc((void**)&net->e4, nb * 16);
   alloc((void**)&net->eA, nb * WIDTH * 2);
   alloc((void**)&net->eB, nb * WIDTH * 2);
-  alloc((void**)&net->partial, (size_t)WG_MAX_BLOCKS * (32 * 9 * 32 + 32) * 4);
+  size_t partial = 0;
+  for (int l = 0; l < NL; ++l)
+    partial = std::max(partial, (size_t)net->wgrad_grid[l] * (L_COS[l] * 9 * L_CIS[l] + L_COS[l]));
+  alloc((void**)&net->partial, partial * 4);
   alloc((void**)&net->red, (size_t)net->red_blocks * 8 * 8);
   alloc((void**)&net->scalars, 8 * 8);
   alloc((void**)&net->Jrow, net->H * 4);
