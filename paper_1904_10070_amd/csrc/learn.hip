@@ -590,12 +590,13 @@ struct GradArgs {
   double scale;
 };
 
-// 64 parameters per block; each of the four wavefronts sums every fourth partial block of
-// them, and the four sums are added in a fixed order
+// 64 parameters per block; each of the GR_WAVES wavefronts sums every GR_WAVES-th partial
+// block of them, and their sums are added in a fixed order
 constexpr int GR_PARAMS = 64;
+constexpr int GR_WAVES = 16;
 
-__global__ __launch_bounds__(256) void grad_reduce_kernel(GradArgs a) {
-  __shared__ double part[4][GR_PARAMS];
+__global__ __launch_bounds__(64 * GR_WAVES) void grad_reduce_kernel(GradArgs a) {
+  __shared__ double part[GR_WAVES][GR_PARAMS];
   const int lane = threadIdx.x & 63, quarter = threadIdx.x >> 6;
   const int p = blockIdx.x * GR_PARAMS + lane;
   const int nw = a.cout * 9 * a.cin;
@@ -612,13 +613,16 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(GradArgs a) {
   const size_t stride = (size_t)a.cos_s * 9 * a.cis + a.cos_s;
   double s = 0.0;
   if (valid) {
-#pragma unroll 8
-    for (int b = quarter; b < a.blocks; b += 4) s += (double)a.partial[b * stride + src];
+#pragma unroll 4
+    for (int b = quarter; b < a.blocks; b += GR_WAVES) s += (double)a.partial[b * stride + src];
   }
   part[quarter][lane] = s;
   __syncthreads();
-  if (quarter == 0 && valid)
-    a.grad[p] = (float)(((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * a.scale);
+  if (quarter == 0 && valid) {
+    double t = 0.0;
+    for (int q = 0; q < GR_WAVES; ++q) t += part[q][lane];
+    a.grad[p] = (float)(t * a.scale);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -741,8 +745,13 @@ struct FragArgs {
   u16* out;
   int slots, cob, wide, transpose, cin, cout;
 };
+// every layer's forward and input-gradient fragments in one launch: job blockIdx.y
+struct FragJobs {
+  FragArgs job[2 * NL - 1];
+};
 
-__global__ __launch_bounds__(256) void frag_kernel(FragArgs a) {
+__global__ __launch_bounds__(256) void frag_kernel(FragJobs jobs) {
+  const FragArgs& a = jobs.job[blockIdx.y];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.slots) return;
   const int i = s & 7, lane = (s >> 3) & 63;
@@ -1457,7 +1466,8 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
     GradArgs ga{net->partial, net->grad + layer_offset(l), wblocks, L_CIS[l], L_COS[l], L_CIN[l],
                 L_COUT[l], scale};
     seq.push_back(make_launch(reinterpret_cast<const void*>(&grad_reduce_kernel),
-                              dim3(blocks_for(layer_params(l), GR_PARAMS)), dim3(256), ga));
+                              dim3(blocks_for(layer_params(l), GR_PARAMS)),
+                              dim3(64 * GR_WAVES), ga));
     if (l > 0) {
       // error signals alternate between two buffers: layer 4 -> eA, 3 -> eB, 2 -> eA, ...
       u16* next = (l == 4 || e == net->eB) ? net->eA : net->eB;
@@ -1469,9 +1479,11 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
 }
 
 void frags_seq(const tlb_cnn* net, std::vector<tlbi_launch>& seq) {
+  FragJobs jobs{};
+  int n = 0, blocks = 1;
   for (int l = 0; l < NL; ++l)
     for (int tr = 0; tr < (l > 0 ? 2 : 1); ++tr) {
-      FragArgs fa{};
+      FragArgs& fa = jobs.job[n++];
       fa.W = net->params + layer_offset(l);
       fa.out = tr ? net->wd[l] : net->wf[l];
       fa.slots = frag_slots(l, tr);
@@ -1480,9 +1492,10 @@ void frags_seq(const tlb_cnn* net, std::vector<tlbi_launch>& seq) {
       fa.cout = L_COUT[l];
       fa.cob = tr ? (L_CIN[l] + 15) / 16 : (L_COUT[l] + 15) / 16;
       fa.wide = tr ? (L_COS[l] == 32) : (L_CIS[l] == 32);
-      seq.push_back(make_launch(reinterpret_cast<const void*>(&frag_kernel),
-                                dim3(blocks_for(fa.slots, 256)), dim3(256), fa));
+      blocks = std::max(blocks, blocks_for(fa.slots, 256));
     }
+  seq.push_back(make_launch(reinterpret_cast<const void*>(&frag_kernel), dim3(blocks, n),
+                            dim3(256), jobs));
 }
 
 int32_t check_batch(const tlb_cnn* net, const float* moments, int32_t n) {
