@@ -389,24 +389,36 @@ struct WgradStrip {
   static constexpr int NA = 9 * (CIS / 8) * 32;
   static constexpr int KA = (NA + WG_THREADS - 1) / WG_THREADS;
   static constexpr bool UNIFORM = (CIS / 8) % 2 == 0;
+  // units of the last round, taken by the highest threads: the products give the lowest
+  // wavefronts the extra (tap, input block) pair, so the SIMDs even out
+  static constexpr int REM = NA - (KA - 1) * WG_THREADS;
   uint4 e;
   uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
   int tap[KA];      // UNIFORM: tap of unit k, 9 where the thread has no unit k
 
+  // first unit of round k (units base .. base + WG_THREADS - 1 by thread)
+  __device__ __forceinline__ static int base_of(int k) {
+    return k < KA - 1 ? k * WG_THREADS : k * WG_THREADS - (WG_THREADS - REM);
+  }
+  __device__ __forceinline__ static int unit_of(int k) {
+    return (k < KA - 1 || (int)threadIdx.x >= WG_THREADS - REM) ? base_of(k) + (int)threadIdx.x
+                                                                : -1;
+  }
   __device__ __forceinline__ void init(int wave) {
     if constexpr (UNIFORM) {
 #pragma unroll
       for (int k = 0; k < KA; ++k) {
-        // (u / 32) / (CIS / 8) with u / 32 = 2 wave + lane / 32 + 8 k: the lane's bit drops
-        const int t = (wave + 4 * k) / (CIS / 16);
-        tap[k] = t < 9 ? t : 9;
+        // (u / 32) / (CIS / 8) with u / 32 = base / 32 + 2 wave + lane / 32, base / 32 even:
+        // the lane's bit drops
+        const bool has = k < KA - 1 || 64 * wave >= WG_THREADS - REM;
+        tap[k] = has ? ((base_of(k) >> 6) + wave) / (CIS / 16) : 9;
       }
     }
   }
   __device__ __forceinline__ int tap_of(int k) const {
     if constexpr (UNIFORM) return tap[k];
-    const int u = threadIdx.x + k * WG_THREADS;
-    return u < NA ? (u >> 5) / (CIS / 8) : 9;
+    const int u = unit_of(k);
+    return u >= 0 ? (u >> 5) / (CIS / 8) : 9;
   }
 
   __device__ __forceinline__ void load(const WgradArgs& a, const StripPos& p) {
@@ -427,7 +439,7 @@ struct WgradStrip {
     for (int k = 0; k < KA; ++k) {
       const int t = tap_of(k);
       if (t < 9) {
-        const int c8 = ((threadIdx.x + k * WG_THREADS) >> 5) % (CIS / 8);
+        const int c8 = (unit_of(k) >> 5) % (CIS / 8);
         const int yy = wrap1(y + t / 3 - 1, a.H);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -468,7 +480,7 @@ struct WgradStrip {
     for (int k = 0; k < KA; ++k) {
       const int t = tap_of(k);
       if (t < 9) {
-        const int c8 = ((threadIdx.x + k * WG_THREADS) >> 5) % (CIS / 8);
+        const int c8 = (unit_of(k) >> 5) % (CIS / 8);
         unsigned w[2][4];  // the two nodes' channels 8 c8 .. + 7, two bf16 per word
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -506,36 +518,47 @@ struct WgradStrip {
 template <int CIS, int COS, bool MOM>
 __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   constexpr int CIB = (CIS + 15) / 16, COB = (COS + 15) / 16;
-  constexpr int NF = 9 * COB * CIB;            // 16 x 16 output fragments
-  constexpr int FPW = (NF + 3) / 4;            // fragments per wavefront
+  // 16 x 16 output fragments (tap t, output block bc, input block bi); a wavefront takes
+  // whole (t, bi) pairs, so that each node operand it reads from LDS serves every bc
+  constexpr int NP = 9 * CIB;            // (tap, input block) pairs
+  constexpr int PPW = (NP + 3) / 4;      // pairs per wavefront
   using Strip = WgradStrip<CIS, COS, MOM>;
   __shared__ __attribute__((aligned(16))) u16 sE[COS * WG_PITCH];
   __shared__ __attribute__((aligned(16))) u16 sA[9 * CIS * WG_PITCH];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 3;
   const int px = lane & 15, g = lane >> 4;
-  f32x4 acc[FPW];
+  f32x4 acc[PPW][COB];
 #pragma unroll
-  for (int k = 0; k < FPW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < PPW; ++k)
+#pragma unroll
+    for (int bc = 0; bc < COB; ++bc) acc[k][bc] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int s0 = (int)((long long)blockIdx.x * a.strips / gridDim.x);
   const int s1 = (int)((long long)(blockIdx.x + 1) * a.strips / gridDim.x);
   auto products = [&]() {
+    bf16x8 A[COB][2];  // the error operand of every output block, both halves of the strip
 #pragma unroll
-    for (int k = 0; k < FPW; ++k) {
-      const int f = wave + 4 * k;
-      if (f < NF) {
-        const int t = f / (COB * CIB), bc = (f / CIB) % COB, bi = f % CIB;
-        const int co = 16 * bc + px, ci = 16 * bi + px;
+    for (int bc = 0; bc < COB; ++bc)
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc)
+        A[bc][kc] = 16 * bc + px < COS ? *reinterpret_cast<const bf16x8*>(
+                                             &sE[wg_at(16 * bc + px, 32 * kc + 8 * g)])
+                                       : zero_frag();
+#pragma unroll
+    for (int k = 0; k < PPW; ++k) {
+      const int pr = wave + 4 * k;
+      if (pr < NP) {
+        const int t = pr / CIB, bi = pr % CIB;
+        const int ci = 16 * bi + px;
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) {
-          const bf16x8 A = co < COS ? *reinterpret_cast<const bf16x8*>(
-                                          &sE[wg_at(co, 32 * kc + 8 * g)])
-                                    : zero_frag();
           const bf16x8 B = ci < CIS ? *reinterpret_cast<const bf16x8*>(
                                           &sA[wg_at(t * CIS + ci, 32 * kc + 8 * g)])
                                     : zero_frag();
-          acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[k], 0, 0, 0);
+#pragma unroll
+          for (int bc = 0; bc < COB; ++bc)
+            acc[k][bc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[bc][kc], B, acc[k][bc], 0, 0, 0);
         }
       }
     }
@@ -558,16 +581,18 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   }
   float* out = a.partial + (size_t)blockIdx.x * (COS * 9 * CIS + COS);
 #pragma unroll
-  for (int k = 0; k < FPW; ++k) {
-    const int f = wave + 4 * k;
-    if (f < NF) {
-      const int t = f / (COB * CIB), bc = (f / CIB) % COB, bi = f % CIB;
+  for (int k = 0; k < PPW; ++k) {
+    const int pr = wave + 4 * k;
+    if (pr < NP) {
+      const int t = pr / CIB, bi = pr % CIB;
       const int ci = 16 * bi + px;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int co = 16 * bc + 4 * g + i;
-        if (co < COS && ci < CIS) out[(co * 9 + t) * CIS + ci] = acc[k][i];
-      }
+      for (int bc = 0; bc < COB; ++bc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int co = 16 * bc + 4 * g + i;
+          if (co < COS && ci < CIS) out[(co * 9 + t) * CIS + ci] = acc[k][bc][i];
+        }
     }
   }
   // bias gradient: the error values of channel 8 w + i sit in wave w's lanes (one node each)
