@@ -103,6 +103,39 @@ def test_gradient_matches_reference(torch_cuda, shape):
         o += nW + co
 
 
+@pytest.mark.parametrize("shape", [(8, 64, 136), (6, 48, 200)])
+def test_forward_and_gradient_with_many_tiles_per_wavefront(torch_cuda, shape):
+    """More 64-node strips (1536, 1152) than weight-gradient workgroups and more 16-node tiles
+    (4608, 3744) than convolution wavefronts on this part, so that each walks several strips
+    or tiles, carrying across rows and samples, with ragged row ends (136 = 2 x 64 + 8,
+    200 = 3 x 64 + 8)."""
+    torch = torch_cuda
+    n, H, W = shape
+    params = params_with_biases(11)
+    m, y = inputs.learn_samples(12, n, H, W)
+    net = make_net(torch, H, W, n, params)
+    mt, yt = torch.tensor(m, device="cuda"), torch.tensor(y, device="cuda")
+    out = net.forward(mt).cpu().numpy().astype(np.float64)
+    _, z = C.forward(params.astype(np.float64), m.astype(np.float64), GEO["r"], GEO["R"], SHIFT, SCALE)
+    ref = z * np.array(OUT_SCALE)
+    e2, ei = rel_l2(out, ref), rel_linf(out, ref)
+    print(f"forward {n}x{H}x{W}: rel L2 {e2:.2e}, rel Linf {ei:.2e}", flush=True)
+    assert e2 <= 1e-3 and ei <= 1e-2
+    loss, grad = net.gradient(mt, yt)
+    L, g_ref, _ = C.loss_and_grad(params.astype(np.float64), m.astype(np.float64),
+                                  y.astype(np.float64), GEO["r"], GEO["R"], SHIFT, SCALE,
+                                  OUT_SCALE, LOSS_W)
+    assert abs(loss - L) <= 1e-4 * L, (loss, L)
+    o = 0
+    for l, (ci, co) in enumerate(C.ARCH):
+        nW = co * 9 * ci
+        for name, sl in (("W", slice(o, o + nW)), ("b", slice(o + nW, o + nW + co))):
+            e = rel_l2(grad[sl].astype(np.float64), g_ref[sl])
+            print(f"layer {l} d{name}: rel L2 {e:.2e}", flush=True)
+            assert e <= 1e-3, (l, name, e)
+        o += nW + co
+
+
 def test_gradient_close_to_exact_network(torch_cuda):
     """Against the exact network (no rounding), whose gradient the oracle pins by finite
     differences: the bfloat16 policy costs about 1 % of the gradient."""
