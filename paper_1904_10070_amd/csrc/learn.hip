@@ -217,7 +217,8 @@ __device__ __forceinline__ void load_tile_mask(const ConvArgs& a, const TileCurs
 }
 
 template <int IN, int COB, int EPI>
-__global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
+__global__ __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+void conv_kernel(ConvArgs a) {
   constexpr int KC = IN == IN_BF32 ? 9 : 3;  // 32-long product chunks
   __shared__ bf16x8 sw[KC * COB * 64];
   const int lane = threadIdx.x & 63;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
   step.set(stride, a.xt, a.H);
   // the first tile's node operand is in flight while the weights are staged
   bf16x8 bf[KC];
-  uint2 mk[COB];  // EPI_MASK: the ReLU mask, loaded with the tile's operand
+  uint2 mk[COB], mk2[COB];  // EPI_MASK: the ReLU masks of alternate tiles, loaded with their operands
   if (t < a.tiles) {
     load_node_operand<IN, KC>(a, cur, px, g, bf);
     if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, cur, px, g, mk);
@@ -247,7 +248,10 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
       bias[b][i] = EPI == EPI_RELU ? a.bias[16 * b + 4 * g + i] : EPI == EPI_OUT ? a.bias[i] : 0.f;
   __syncthreads();
   double ps0 = 0.0, ps1 = 0.0, pa = 0.0;  // EPI_OUT projection sums of this lane
-  for (; t < a.tiles; t += stride) {
+  // one tile: its products, the next tile's operand and mask (into mnext), its epilogue (with
+  // mnow).  The loop alternates the two mask registers, so no copy makes the epilogue wait for
+  // the loads just issued.
+  auto tile_step = [&](const uint2 (&mnow)[COB], uint2 (&mnext)[COB]) {
     const int y = cur.y, n = cur.n;
     const int x = cur.xb * 16 + px;
     const bool live = x < a.W;
@@ -269,16 +273,12 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
                                                          acc[b], 0, 0, 0);
     // the next tile's operand and mask (this tile's again after the last: unused, but
     // loading them unconditionally keeps the epilogue's wait from covering these loads)
-    uint2 mcur[COB];  // this tile's mask, kept before the next one's is loaded
-    if constexpr (EPI == EPI_MASK)
-#pragma unroll
-      for (int b = 0; b < COB; ++b) mcur[b] = mk[b];
     TileCursor next = cur;
     if (t + stride < a.tiles) next.advance(step, a.xt, a.H);
     load_node_operand<IN, KC>(a, next, px, g, bf);
-    if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, next, px, g, mk);
+    if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, next, px, g, mnext);
     cur = next;
-    if (!live) continue;
+    if (!live) return;
     if constexpr (EPI == EPI_OUT) {
       if (g == 0) {
         float4 o;
@@ -302,8 +302,8 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[b][i] + bias[b][i], 0.0f);
         } else {
-          const u16 m4[4] = {(u16)(mcur[b].x & 0xFFFF), (u16)(mcur[b].x >> 16),
-                             (u16)(mcur[b].y & 0xFFFF), (u16)(mcur[b].y >> 16)};
+          const u16 m4[4] = {(u16)(mnow[b].x & 0xFFFF), (u16)(mnow[b].x >> 16),
+                             (u16)(mnow[b].y & 0xFFFF), (u16)(mnow[b].y >> 16)};
 #pragma unroll
           for (int i = 0; i < 4; ++i) v[i] = from_bf16(m4[i]) > 0.0f ? acc[b][i] : 0.0f;
         }
@@ -313,6 +313,13 @@ __global__ __launch_bounds__(CONV_THREADS) void conv_kernel(ConvArgs a) {
         *reinterpret_cast<uint2*>(static_cast<u16*>(a.out) + opix * 32 + co) = st;
       }
     }
+  };
+  while (t < a.tiles) {
+    tile_step(mk, mk2);
+    t += stride;
+    if (t >= a.tiles) break;
+    tile_step(mk2, mk);
+    t += stride;
   }
   if constexpr (EPI == EPI_OUT) {
     if (a.proj) {  // uniform: every thread takes part in the fixed-order block sums
