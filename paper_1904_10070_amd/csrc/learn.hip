@@ -362,46 +362,51 @@ struct WgradArgs {
   int n, H, W, xs, strips;  // xs = ceil(W / 64) strips per row; strips = n H xs
 };
 
-// A strip s = (n H + y) xs + xb (64 nodes of one row) as its coordinates; the strips of a
-// workgroup are consecutive, so the next one is one carry away.
+// A strip s = (n xs + xb) H + y (64 nodes of one row; rows vary fastest) as its
+// coordinates; the strips of a workgroup are consecutive, so the next one is one carry away,
+// and mostly the next row of the same column.
 struct StripPos {
   int xb, y, n;
   __device__ __forceinline__ void set(int s, int xs, int H) {
-    xb = s % xs;
-    const int rest = s / xs;
-    y = rest % H;
-    n = rest / H;
+    y = s % H;
+    const int rest = s / H;
+    xb = rest % xs;
+    n = rest / xs;
   }
   __device__ __forceinline__ void next(int xs, int H) {
-    if (++xb == xs) {
-      xb = 0;
-      if (++y == H) {
-        y = 0;
+    if (++y == H) {
+      y = 0;
+      if (++xb == xs) {
+        xb = 0;
         ++n;
       }
     }
   }
 };
 
+// The input tiles in LDS form a window of three rows: tap (dy, dx) of the strip in row y
+// (input row y + dy - 1, nodes shifted by dx - 1) sits in tile 3 slot + dx with slot =
+// (y + dy + 2) mod 3.  The next row's strip of the same column shares two of the rows, so
+// it stages only the new one (its three taps dy = 2); a strip that starts a column stages
+// all nine taps.
+__device__ __forceinline__ int wg_tile(int y, int t) { return ((y + t / 3 + 2) % 3) * 3 + t % 3; }
+
 // The global loads of one strip, all issued before any is used: the error tile (thread u <
-// (COS/8) 64 takes node u % 64, channels 8 (u / 64) .. + 7) and the nine shifted input tiles,
-// by pairs of neighbouring nodes (unit u: nodes 2 (u % 32) and +1, channels 8 c8 .. + 7 with
-// c8 = (u / 32) % (CIS / 8), tap (u / 32) / (CIS / 8), so that each LDS store of the
-// transposed tile writes two consecutive nodes), KA units per thread; the error is zero
-// beyond the row's end.  With CIS / 8 even, the 64 units of a wavefront share their tap:
-// the taps are then found once per thread, from the wavefront index, and are scalars.
-template <int CIS, int COS, bool MOM>
-struct WgradStrip {
-  static constexpr int NE = (COS / 8) * 64;
-  static constexpr int NA = 9 * (CIS / 8) * 32;
+// (COS/8) 64 takes node u % 64, channels 8 (u / 64) .. + 7) and the input taps to stage, by
+// pairs of neighbouring nodes (unit u: nodes 2 (u % 32) and +1, channels 8 c8 .. + 7 with
+// c8 = (u / 32) % (CIS / 8), tap T0 + (u / 32) / (CIS / 8), so that each LDS store of the
+// transposed tile writes two consecutive nodes); the error is zero beyond the row's end.
+// With CIS / 8 even, the 64 units of a wavefront share their tap: the taps are then found
+// once per thread, from the wavefront index, and are scalars.  The partial last round of
+// units goes to the highest threads: the products give the lowest wavefronts the extra
+// (tap, input block) pair, so the SIMDs even out.
+template <int CIS, int NTAP, int T0>
+struct WgradUnits {
+  static constexpr int NA = NTAP * (CIS / 8) * 32;
   static constexpr int KA = (NA + WG_THREADS - 1) / WG_THREADS;
-  static constexpr bool UNIFORM = (CIS / 8) % 2 == 0;
-  // units of the last round, taken by the highest threads: the products give the lowest
-  // wavefronts the extra (tap, input block) pair, so the SIMDs even out
   static constexpr int REM = NA - (KA - 1) * WG_THREADS;
-  uint4 e;
-  uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
-  int tap[KA];      // UNIFORM: tap of unit k, 9 where the thread has no unit k
+  static constexpr bool UNIFORM = (CIS / 8) % 2 == 0;
+  int tap[KA];  // UNIFORM: tap of unit k, 9 where the thread has no unit k
 
   // first unit of round k (units base .. base + WG_THREADS - 1 by thread)
   __device__ __forceinline__ static int base_of(int k) {
@@ -418,35 +423,60 @@ struct WgradStrip {
         // (u / 32) / (CIS / 8) with u / 32 = base / 32 + 2 wave + lane / 32, base / 32 even:
         // the lane's bit drops
         const bool has = k < KA - 1 || 64 * wave >= WG_THREADS - REM;
-        tap[k] = has ? ((base_of(k) >> 6) + wave) / (CIS / 16) : 9;
+        tap[k] = has ? T0 + ((base_of(k) >> 6) + wave) / (CIS / 16) : 9;
       }
     }
   }
   __device__ __forceinline__ int tap_of(int k) const {
     if constexpr (UNIFORM) return tap[k];
     const int u = unit_of(k);
-    return u >= 0 ? (u >> 5) / (CIS / 8) : 9;
+    return u >= 0 ? T0 + (u >> 5) / (CIS / 8) : 9;
+  }
+};
+
+template <int CIS, int COS, bool MOM>
+struct WgradStrip {
+  static constexpr int NE = (COS / 8) * 64;
+  using Full = WgradUnits<CIS, 9, 0>;  // a strip that starts a column: all nine taps
+  using Row = WgradUnits<CIS, 3, 6>;   // the next row's strip: the new row's three taps
+  static constexpr int KA = Full::KA;
+  // every round starts at a multiple of 32 (CIS / 8) units, so a thread's node pair and
+  // channel group are the same in both modes; only the taps differ
+  static_assert(Full::REM % (32 * (CIS / 8)) == 0 && Row::REM % (32 * (CIS / 8)) == 0,
+                "round bases");
+  uint4 e;
+  uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
+  Full full;
+  Row row;
+
+  __device__ __forceinline__ void init(int wave) {
+    full.init(wave);
+    row.init(wave);
+  }
+  // tap of this thread's unit in round k (9: none) when staging all taps or the new row's
+  __device__ __forceinline__ int tap_of(int k, bool all) const {
+    const int tr = k < Row::KA ? row.tap_of(k) : 9;
+    return all ? full.tap_of(k) : tr;
   }
 
-  __device__ __forceinline__ void load(const WgradArgs& a, const StripPos& p) {
+  __device__ __forceinline__ void load(const WgradArgs& a, const StripPos& p, bool all) {
     const int y = p.y, n = p.n;
     const int x0 = p.xb * 64;
-    const int jp = threadIdx.x & 31;
+    const int jp = threadIdx.x & 31, c8 = (threadIdx.x >> 5) % (CIS / 8);
     e = make_uint4(0, 0, 0, 0);
     // bf16 tensors: n H W < 2^28 nodes, checked when the network is created; each load takes
     // its row's start (uniform) and a 32-bit byte offset within the row
     if (threadIdx.x < NE) {
-      const int j = threadIdx.x & 63, c8 = threadIdx.x >> 6;
+      const int j = threadIdx.x & 63, c8e = threadIdx.x >> 6;
       const char* erow =
           reinterpret_cast<const char*>(a.e) + (size_t)((n * a.H + y) * a.W) * COS * 2;
       if (x0 + j < a.W)
-        e = *reinterpret_cast<const uint4*>(erow + (unsigned)(((x0 + j) * COS + 8 * c8) * 2));
+        e = *reinterpret_cast<const uint4*>(erow + (unsigned)(((x0 + j) * COS + 8 * c8e) * 2));
     }
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-      const int t = tap_of(k);
+      const int t = tap_of(k, all);
       if (t < 9) {
-        const int c8 = (unit_of(k) >> 5) % (CIS / 8);
         const int yy = wrap1(y + t / 3 - 1, a.H);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -468,26 +498,26 @@ struct WgradStrip {
     }
   }
 
-  // transposed into LDS: sE[o][j] = e[n][y][x0 + j][o], sA[t][i][j] = a[n][y+dy][x0+j+dx][i];
-  // bsum[i] accumulates this thread's error values (channel 8 (tid / 64) + i)
-  __device__ __forceinline__ void store(const WgradArgs& a, const StripPos& p, u16* sE, u16* sA,
-                                        float (&bsum)[8]) const {
+  // transposed into LDS: sE[o][j] = e[n][y][x0 + j][o]; tile wg_tile(y, t) of sA [i][j] =
+  // a[n][y + dy - 1][x0 + j + dx - 1][i]; bsum[i] accumulates this thread's error values
+  // (channel 8 (tid / 64) + i)
+  __device__ __forceinline__ void store(const WgradArgs& a, const StripPos& p, bool all, u16* sE,
+                                        u16* sA, float (&bsum)[8]) const {
     if (threadIdx.x < NE) {
-      const int j = threadIdx.x & 63, c8 = threadIdx.x >> 6;
+      const int j = threadIdx.x & 63, c8e = threadIdx.x >> 6;
       const unsigned w4[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const u16 v = (u16)((w4[i >> 1] >> (16 * (i & 1))) & 0xFFFF);
-        sE[wg_at(8 * c8 + i, j)] = v;
+        sE[wg_at(8 * c8e + i, j)] = v;
         bsum[i] += from_bf16(v);
       }
     }
-    const int jp = threadIdx.x & 31;
+    const int jp = threadIdx.x & 31, c8 = (threadIdx.x >> 5) % (CIS / 8);
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-      const int t = tap_of(k);
+      const int t = tap_of(k, all);
       if (t < 9) {
-        const int c8 = (unit_of(k) >> 5) % (CIS / 8);
         unsigned w[2][4];  // the two nodes' channels 8 c8 .. + 7, two bf16 per word
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -509,13 +539,14 @@ struct WgradStrip {
         }
         // channel 2 i: the low halves of the two nodes' word i; channel 2 i + 1: the high
         // halves (byte selectors 0-3 take the second operand's bytes, 4-7 the first's)
+        const int tile = wg_tile(p.y, t);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           // rows 2 i and 2 i + 1 of the group share their chunk order
-          unsigned* row =
-              reinterpret_cast<unsigned*>(sA + wg_at(t * CIS + 8 * c8 + 2 * i, 2 * jp));
-          row[0] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x05040100u);
-          row[WG_PITCH / 2] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x07060302u);
+          unsigned* r =
+              reinterpret_cast<unsigned*>(sA + wg_at(tile * CIS + 8 * c8 + 2 * i, 2 * jp));
+          r[0] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x05040100u);
+          r[WG_PITCH / 2] = __builtin_amdgcn_perm(w[1][i], w[0][i], 0x07060302u);
         }
       }
     }
@@ -543,7 +574,7 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int s0 = (int)((long long)blockIdx.x * a.strips / gridDim.x);
   const int s1 = (int)((long long)(blockIdx.x + 1) * a.strips / gridDim.x);
-  auto products = [&]() {
+  auto products = [&](int y) {
     bf16x8 A[COB][2];  // the error operand of every output block, both halves of the strip
 #pragma unroll
     for (int bc = 0; bc < COB; ++bc)
@@ -561,7 +592,7 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) {
           const bf16x8 B = ci < CIS ? *reinterpret_cast<const bf16x8*>(
-                                          &sA[wg_at(t * CIS + ci, 32 * kc + 8 * g)])
+                                          &sA[wg_at(wg_tile(y, t) * CIS + ci, 32 * kc + 8 * g)])
                                     : zero_frag();
 #pragma unroll
           for (int bc = 0; bc < COB; ++bc)
@@ -574,17 +605,20 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   st.init(wave);
   StripPos pos, nxt;
   pos.set(s0, a.xs, a.H);
-  if (s0 < s1) st.load(a, pos);
+  bool all = true;  // the strip stages all nine taps (the workgroup's first, or a new column)
+  if (s0 < s1) st.load(a, pos, all);
   for (int s = s0; s < s1; ++s) {
-    st.store(a, pos, sE, sA, bsum);
+    st.store(a, pos, all, sE, sA, bsum);
     // the next strip's loads are in flight during this strip's products
     nxt = pos;
     nxt.next(a.xs, a.H);
-    if (s + 1 < s1) st.load(a, nxt);
+    const bool nall = nxt.y == 0;
+    if (s + 1 < s1) st.load(a, nxt, nall);
+    __syncthreads();
+    products(pos.y);
+    __syncthreads();
     pos = nxt;
-    __syncthreads();
-    products();
-    __syncthreads();
+    all = nall;
   }
   float* out = a.partial + (size_t)blockIdx.x * (COS * 9 * CIS + COS);
 #pragma unroll
