@@ -141,27 +141,23 @@ struct ConvArgs {
 constexpr int CONV_THREADS = 256;
 constexpr int CONV_WAVES = CONV_THREADS / 64;
 
-// A tile index t = (n H + y) xt + xb as its coordinates, advanced by a fixed stride with one
-// carry per coordinate instead of divisions (the stride's own coordinates are below xt and H).
+// A tile index t = (n xt + xb) H + y (16 nodes of one row; rows vary fastest) as its
+// coordinates; a wavefront walks consecutive tiles, mostly down one column.
 struct TileCursor {
   int xb, y, n;
   __device__ __forceinline__ void set(int t, int xt, int H) {
-    xb = t % xt;
-    const int rest = t / xt;
-    y = rest % H;
-    n = rest / H;
+    y = t % H;
+    const int rest = t / H;
+    xb = rest % xt;
+    n = rest / xt;
   }
-  __device__ __forceinline__ void advance(const TileCursor& step, int xt, int H) {
-    xb += step.xb;
-    y += step.y;
-    n += step.n;
-    if (xb >= xt) {
-      xb -= xt;
-      ++y;
-    }
-    if (y >= H) {
-      y -= H;
-      ++n;
+  __device__ __forceinline__ void next(int xt, int H) {
+    if (++y == H) {
+      y = 0;
+      if (++xb == xt) {
+        xb = 0;
+        ++n;
+      }
     }
   }
 };
@@ -169,7 +165,7 @@ struct TileCursor {
 // The node operand of one tile: for each 32-long chunk c, this lane's 8 products -- tap c
 // with channels 8g..8g+7 (32-channel input), or tap 4c+g with all 8 channels (8-channel
 // input; taps 9..11 are zero padding).
-template <int IN, int KC>
+template <int IN, int KC, int C0 = 0>
 __device__ __forceinline__ void load_node_operand(const ConvArgs& a, const TileCursor& tc,
                                                   int px, int g, bf16x8 (&bf)[KC]) {
   const int y = tc.y, n = tc.n;
@@ -183,7 +179,7 @@ __device__ __forceinline__ void load_node_operand(const ConvArgs& a, const TileC
     cols[d] = min(wrap1(x + d - 1, a.W), a.W - 1);
   }
 #pragma unroll
-  for (int c = 0; c < KC; ++c) {
+  for (int c = C0; c < KC; ++c) {
     const int tap = IN == IN_BF32 ? c : 4 * c + g;
     bf[c] = zero_frag();
     if (tap < 9) {
@@ -224,15 +220,16 @@ void conv_kernel(ConvArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // tiles are per wave
   const int px = lane & 15, g = lane >> 4;
-  const int stride = gridDim.x * CONV_WAVES;
-  int t = blockIdx.x * CONV_WAVES + wave;
-  TileCursor cur, step;
+  // each wavefront takes a contiguous range of tiles
+  const int nw = gridDim.x * CONV_WAVES, w = blockIdx.x * CONV_WAVES + wave;
+  int t = (int)((long long)w * a.tiles / nw);
+  const int t_end = (int)((long long)(w + 1) * a.tiles / nw);
+  TileCursor cur;
   cur.set(t, a.xt, a.H);
-  step.set(stride, a.xt, a.H);
   // the first tile's node operand is in flight while the weights are staged
   bf16x8 bf[KC];
   uint2 mk[COB], mk2[COB];  // EPI_MASK: the ReLU masks of alternate tiles, loaded with their operands
-  if (t < a.tiles) {
+  if (t < t_end) {
     load_node_operand<IN, KC>(a, cur, px, g, bf);
     if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, cur, px, g, mk);
   }
@@ -272,10 +269,20 @@ void conv_kernel(ConvArgs a) {
         acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sw[(c * COB + b) * 64 + lane], bf[c],
                                                          acc[b], 0, 0, 0);
     // the next tile's operand and mask (this tile's again after the last: unused, but
-    // loading them unconditionally keeps the epilogue's wait from covering these loads)
+    // loading them unconditionally keeps the epilogue's wait from covering these loads).
+    // With 32-channel inputs (chunk c = tap c = 3 dy + dx) the next row's tile of the same
+    // column shares taps: its dy = 0, 1 are this tile's dy = 1, 2, and only the new row's
+    // three taps are loaded.
     TileCursor next = cur;
-    if (t + stride < a.tiles) next.advance(step, a.xt, a.H);
-    load_node_operand<IN, KC>(a, next, px, g, bf);
+    const bool more = t + 1 < t_end;
+    if (more) next.next(a.xt, a.H);
+    if (IN == IN_BF32 && more && next.y != 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) bf[c] = bf[c + 3];
+      load_node_operand<IN, KC, IN == IN_BF32 ? 6 : 0>(a, next, px, g, bf);
+    } else {
+      load_node_operand<IN, KC>(a, next, px, g, bf);
+    }
     if constexpr (EPI == EPI_MASK) load_tile_mask<COB>(a, next, px, g, mnext);
     cur = next;
     if (!live) return;
@@ -314,12 +321,11 @@ void conv_kernel(ConvArgs a) {
       }
     }
   };
-  while (t < a.tiles) {
+  while (t < t_end) {
     tile_step(mk, mk2);
-    t += stride;
-    if (t >= a.tiles) break;
+    if (++t >= t_end) break;
     tile_step(mk2, mk);
-    t += stride;
+    ++t;
   }
   if constexpr (EPI == EPI_OUT) {
     if (a.proj) {  // uniform: every thread takes part in the fixed-order block sums
