@@ -116,6 +116,26 @@ __device__ __forceinline__ bf16x8 features(const Features& F, float4 m, int row)
   return v;
 }
 
+// the eight bf16 input features of every node of a batch: out[i][p] from the moments of
+// sample idx[i] (NULL: i) at node p
+struct FeatArgs {
+  const float* m;  // float4 moments [*][H][W]
+  const int32_t* idx;
+  u16* out;        // [n][H][W][8]
+  Features F;
+  int n, H, W;
+};
+
+// one workgroup per (row blockIdx.x, batch slot blockIdx.y)
+__global__ __launch_bounds__(128) void features_kernel(FeatArgs a) {
+  const int y = blockIdx.x, slot = blockIdx.y;
+  const int smp = a.idx ? a.idx[slot] : slot;
+  // n H W < 2^28, checked when the network is created
+  const float4* src = reinterpret_cast<const float4*>(a.m) + ((size_t)smp * a.H + y) * a.W;
+  bf16x8* dst = reinterpret_cast<bf16x8*>(a.out) + ((size_t)slot * a.H + y) * a.W;
+  for (int x = threadIdx.x; x < a.W; x += 128) dst[x] = features(a.F, src[x], y);
+}
+
 // ------------------------------------------------------------------------------------------
 // convolution (forward and input gradient)
 
@@ -1397,6 +1417,7 @@ struct tlb_cnn {
   u16* act[4];
   float* z;
   u16* e4;
+  u16* feat;           // the input features of the batch, bf16 [n][HW][8]
   u16* eA;
   u16* eB;
   float* partial;      // weight-gradient partials
@@ -1448,7 +1469,9 @@ int conv_variant(int in, int epi) {
 
 const void* conv_fn(int in, int cob, int epi) {
   if (in == IN_MOM) return reinterpret_cast<const void*>(&conv_kernel<IN_MOM, 2, EPI_RELU>);
-  if (in == IN_BF8) return reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_MASK>);
+  if (in == IN_BF8)
+    return epi == EPI_RELU ? reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_RELU>)
+                           : reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_MASK>);
   if (epi == EPI_OUT) return reinterpret_cast<const void*>(&conv_kernel<IN_BF32, 1, EPI_OUT>);
   if (epi == EPI_MASK) return reinterpret_cast<const void*>(&conv_kernel<IN_BF32, 2, EPI_MASK>);
   (void)cob;
@@ -1482,10 +1505,26 @@ const float* bias_of(const tlb_cnn* net, int l) {
 }
 
 // forward of n samples: moments (sample idx[i]) -> act[0..3] -> z
+// the input features of every node of the batch, once (the first layer's convolution and
+// weight gradient read them as an 8-channel input)
+tlbi_launch features_launch(const tlb_cnn* net, const float* moments, const int32_t* idx, int n) {
+  FeatArgs fa{};
+  fa.m = moments;
+  fa.idx = idx;
+  fa.out = net->feat;
+  fa.F = make_features(net);
+  fa.n = n;
+  fa.H = net->H;
+  fa.W = net->W;
+  return make_launch(reinterpret_cast<const void*>(&features_kernel), dim3(net->H, n), dim3(128),
+                     fa);
+}
+
 void forward_seq(const tlb_cnn* net, const float* moments, const int32_t* idx, int n,
                  std::vector<tlbi_launch>& seq) {
-  seq.push_back(conv_launch(net, IN_MOM, 2, EPI_RELU, moments, idx, net->wf[0], bias_of(net, 0),
-                            nullptr, net->act[0], n));
+  seq.push_back(features_launch(net, moments, idx, n));
+  seq.push_back(conv_launch(net, IN_BF8, 2, EPI_RELU, net->feat, nullptr, net->wf[0],
+                            bias_of(net, 0), nullptr, net->act[0], n));
   for (int l = 1; l < 4; ++l)
     seq.push_back(conv_launch(net, IN_BF32, 2, EPI_RELU, net->act[l - 1], nullptr, net->wf[l],
                               bias_of(net, l), nullptr, net->act[l], n));
@@ -1494,7 +1533,7 @@ void forward_seq(const tlb_cnn* net, const float* moments, const int32_t* idx, i
 }
 
 const void* wgrad_fn(int l) {
-  if (l == 0) return reinterpret_cast<const void*>(&wgrad_kernel<8, 32, true>);
+  if (l == 0) return reinterpret_cast<const void*>(&wgrad_kernel<8, 32, false>);
   if (l == 4) return reinterpret_cast<const void*>(&wgrad_kernel<32, 8, false>);
   return reinterpret_cast<const void*>(&wgrad_kernel<32, 32, false>);
 }
@@ -1524,8 +1563,8 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
   for (int l = NL - 1; l >= 0; --l) {
     WgradArgs wa{};
     wa.e = e;
-    wa.a = l == 0 ? static_cast<const void*>(moments) : static_cast<const void*>(net->act[l - 1]);
-    wa.idx = l == 0 ? idx : nullptr;
+    wa.a = l == 0 ? static_cast<const void*>(net->feat) : static_cast<const void*>(net->act[l - 1]);
+    wa.idx = nullptr;
     wa.partial = net->partial;
     wa.F = make_features(net);
     wa.n = n;
@@ -1733,8 +1772,8 @@ bool graph_matches(const tlb_cnn* net, const tlb_grid* g) {
 }
 
 void free_net(tlb_cnn* net) {
-  void* bufs[] = {net->params, net->grad, net->mom, net->vel, net->z, net->e4, net->eA,
-                  net->eB, net->partial, net->red, net->scalars, net->Jrow, net->proj};
+  void* bufs[] = {net->params, net->grad, net->mom, net->vel, net->z, net->e4, net->feat,
+                  net->eA, net->eB, net->partial, net->red, net->scalars, net->Jrow, net->proj};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int l = 0; l < NL; ++l) {
@@ -1833,6 +1872,7 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   }
   for (int l = 0; l < 4; ++l) alloc((void**)&net->act[l], nb * WIDTH * 2);
   alloc((void**)&net->z, nb * 16);
+  alloc((void**)&net->feat, nb * 16);
   alloc((void**)&net->e4, nb * 16);
   alloc((void**)&net->eA, nb * WIDTH * 2);
   alloc((void**)&net->eB, nb * WIDTH * 2);
