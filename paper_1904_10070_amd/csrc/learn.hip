@@ -139,23 +139,16 @@ __global__ __launch_bounds__(128) void features_kernel(FeatArgs a) {
 // ------------------------------------------------------------------------------------------
 // convolution (forward and input gradient)
 
-enum { IN_BF32 = 0, IN_BF8 = 1, IN_MOM = 2 };       // 32-channel / 8-channel bf16, raw moments
+enum { IN_BF32 = 0, IN_BF8 = 1 };                  // 32-channel / 8-channel bf16 input
 enum { EPI_RELU = 0, EPI_OUT = 1, EPI_MASK = 2 };   // bias+ReLU, bias (FP32 out), ReLU mask
 
 struct ConvArgs {
-  const void* in;        // bf16 [n][H][W][32 or 8], or float [*][H][W][4] moments
-  const int32_t* idx;    // moments: sample of each batch slot (NULL = identity)
+  const void* in;        // bf16 [n][H][W][32 or 8]
   const bf16x8* w;       // weight fragments [kc][cob][64 lanes]
   const float* bias;     // [c_out] (EPI_RELU, EPI_OUT)
   const u16* mask;       // EPI_MASK: activation whose positive entries pass, [n][H][W][32]
   void* out;             // bf16 [n][H][W][32], or float [n][H][W][4] (EPI_OUT)
-  Features F;
   int n, H, W, xt, tiles;  // xt = ceil(W / 16) node groups per row; tiles = n H xt
-  // EPI_OUT, optional (proj != NULL): per-block sums of area-weighted corrections,
-  // proj[block] = (sum a z0 s0, sum a z1 s1, sum a), area[H] the node area of each row
-  double* proj;
-  const double* area;
-  float s0, s1;
 };
 
 constexpr int CONV_THREADS = 256;
@@ -208,15 +201,10 @@ __device__ __forceinline__ void load_node_operand(const ConvArgs& a, const TileC
       const int xx = dx == 0 ? cols[0] : dx == 1 ? cols[1] : cols[2];
       // bf16 activations: n H W < 2^28 nodes, checked when the network is created
       const int pix = (n * a.H + yy) * a.W + xx;
-      if constexpr (IN == IN_BF32) {
+      if constexpr (IN == IN_BF32)
         bf[c] = static_cast<const bf16x8*>(a.in)[(size_t)pix * 4 + g];
-      } else if constexpr (IN == IN_BF8) {
+      else
         bf[c] = static_cast<const bf16x8*>(a.in)[pix];
-      } else {
-        const int smp = a.idx ? a.idx[n] : n;
-        const size_t mp = ((size_t)smp * a.H + yy) * a.W + xx;
-        bf[c] = features(a.F, static_cast<const float4*>(a.in)[mp], yy);
-      }
     }
   }
 }
@@ -264,7 +252,6 @@ void conv_kernel(ConvArgs a) {
     for (int i = 0; i < 4; ++i)
       bias[b][i] = EPI == EPI_RELU ? a.bias[16 * b + 4 * g + i] : EPI == EPI_OUT ? a.bias[i] : 0.f;
   __syncthreads();
-  double ps0 = 0.0, ps1 = 0.0, pa = 0.0;  // EPI_OUT projection sums of this lane
   // one tile: its products, the next tile's operand and mask (into mnext), its epilogue (with
   // mnow).  The loop alternates the two mask registers, so no copy makes the epilogue wait for
   // the loads just issued.
@@ -274,11 +261,6 @@ void conv_kernel(ConvArgs a) {
     const bool live = x < a.W;
     // lane holds node x, output channels 16 b + 4 g + i
     const size_t opix = ((size_t)n * a.H + y) * a.W + x;
-    // the row area is loaded before the next tile's operands, which then stay in flight
-    // while the epilogue waits for it
-    double ar = 0.0;
-    if constexpr (EPI == EPI_OUT)
-      if (a.proj) ar = a.area[y];
     f32x4 acc[COB];
 #pragma unroll
     for (int b = 0; b < COB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -314,11 +296,6 @@ void conv_kernel(ConvArgs a) {
         o.z = acc[0][2] + bias[0][2];
         o.w = acc[0][3] + bias[0][3];
         static_cast<float4*>(a.out)[opix] = o;
-        if (a.proj) {
-          ps0 += ar * (double)(o.x * a.s0);
-          ps1 += ar * (double)(o.y * a.s1);
-          pa += ar;
-        }
       }
     } else {
 #pragma unroll
@@ -347,28 +324,6 @@ void conv_kernel(ConvArgs a) {
     tile_step(mk2, mk);
     ++t;
   }
-  if constexpr (EPI == EPI_OUT) {
-    if (a.proj) {  // uniform: every thread takes part in the fixed-order block sums
-      __shared__ double sh[CONV_WAVES][3];
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        ps0 += __shfl_xor(ps0, d, 64);
-        ps1 += __shfl_xor(ps1, d, 64);
-        pa += __shfl_xor(pa, d, 64);
-      }
-      if (lane == 0) {
-        sh[wave][0] = ps0;
-        sh[wave][1] = ps1;
-        sh[wave][2] = pa;
-      }
-      __syncthreads();
-      if (threadIdx.x < 3) {
-        double v = 0.0;
-        for (int w = 0; w < CONV_WAVES; ++w) v += sh[w][threadIdx.x];
-        a.proj[3 * blockIdx.x + threadIdx.x] = v;
-      }
-    }
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -381,10 +336,8 @@ constexpr int WG_THREADS = 256;
 
 struct WgradArgs {
   const u16* e;        // error signal bf16 [n][H][W][COS]
-  const void* a;       // layer input: bf16 [n][H][W][CIS], or float moments [*][H][W][4]
-  const int32_t* idx;  // moments: sample of each batch slot (NULL = identity)
+  const u16* a;        // layer input bf16 [n][H][W][CIS]
   float* partial;      // [gridDim.x][COS * 9 * CIS + COS]
-  Features F;
   int n, H, W, xs, strips;  // xs = ceil(W / 64) strips per row; strips = n H xs
 };
 
@@ -460,7 +413,7 @@ struct WgradUnits {
   }
 };
 
-template <int CIS, int COS, bool MOM>
+template <int CIS, int COS>
 struct WgradStrip {
   static constexpr int NE = (COS / 8) * 64;
   using Full = WgradUnits<CIS, 9, 0>;  // a strip that starts a column: all nine taps
@@ -471,7 +424,7 @@ struct WgradStrip {
   static_assert(Full::REM % (32 * (CIS / 8)) == 0 && Row::REM % (32 * (CIS / 8)) == 0,
                 "round bases");
   uint4 e;
-  uint4 av[KA][2];  // bf16 inputs, or the float moments (MOM), of the two nodes
+  uint4 av[KA][2];  // bf16 inputs of the two nodes
   Full full;
   Row row;
 
@@ -509,16 +462,9 @@ struct WgradStrip {
           // one wrap is exact for the row's nodes (x0 + 2 jp + h < W); those past its end,
           // whose error is zero, read the row's last node
           const int xx = min(wrap1(x0 + 2 * jp + h + t % 3 - 1, a.W), a.W - 1);
-          if constexpr (MOM) {
-            const int smp = a.idx ? a.idx[n] : n;
-            const float4 m = static_cast<const float4*>(a.a)[((size_t)smp * a.H + yy) * a.W + xx];
-            av[k][h] = make_uint4(__float_as_uint(m.x), __float_as_uint(m.y),
-                                  __float_as_uint(m.z), __float_as_uint(m.w));
-          } else {
-            const char* arow =
-                static_cast<const char*>(a.a) + (size_t)((n * a.H + yy) * a.W) * CIS * 2;
-            av[k][h] = *reinterpret_cast<const uint4*>(arow + (unsigned)((xx * CIS + 8 * c8) * 2));
-          }
+          const char* arow =
+              reinterpret_cast<const char*>(a.a) + (size_t)((n * a.H + yy) * a.W) * CIS * 2;
+          av[k][h] = *reinterpret_cast<const uint4*>(arow + (unsigned)((xx * CIS + 8 * c8) * 2));
         }
       }
     }
@@ -544,25 +490,9 @@ struct WgradStrip {
     for (int k = 0; k < KA; ++k) {
       const int t = tap_of(k, all);
       if (t < 9) {
-        unsigned w[2][4];  // the two nodes' channels 8 c8 .. + 7, two bf16 per word
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if constexpr (MOM) {
-            const int yy = wrap1(p.y + t / 3 - 1, a.H);
-            const float4 m = make_float4(__uint_as_float(av[k][h].x), __uint_as_float(av[k][h].y),
-                                         __uint_as_float(av[k][h].z), __uint_as_float(av[k][h].w));
-            float x[8];
-            features_f(a.F, m, yy, x);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              w[h][i] = (unsigned)to_bf16(x[2 * i]) | ((unsigned)to_bf16(x[2 * i + 1]) << 16);
-          } else {
-            w[h][0] = av[k][h].x;
-            w[h][1] = av[k][h].y;
-            w[h][2] = av[k][h].z;
-            w[h][3] = av[k][h].w;
-          }
-        }
+        // the two nodes' channels 8 c8 .. + 7, two bf16 per word
+        const unsigned w[2][4] = {{av[k][0].x, av[k][0].y, av[k][0].z, av[k][0].w},
+                                  {av[k][1].x, av[k][1].y, av[k][1].z, av[k][1].w}};
         // channel 2 i: the low halves of the two nodes' word i; channel 2 i + 1: the high
         // halves (byte selectors 0-3 take the second operand's bytes, 4-7 the first's)
         const int tile = wg_tile(p.y, t);
@@ -579,14 +509,14 @@ struct WgradStrip {
   }
 };
 
-template <int CIS, int COS, bool MOM>
+template <int CIS, int COS>
 __global__ __launch_bounds__(WG_THREADS) void wgrad_kernel(WgradArgs a) {
   constexpr int CIB = (CIS + 15) / 16, COB = (COS + 15) / 16;
   // 16 x 16 output fragments (tap t, output block bc, input block bi); a wavefront takes
   // whole (t, bi) pairs, so that each node operand it reads from LDS serves every bc
   constexpr int NP = 9 * CIB;            // (tap, input block) pairs
   constexpr int PPW = (NP + 3) / 4;      // pairs per wavefront
-  using Strip = WgradStrip<CIS, COS, MOM>;
+  using Strip = WgradStrip<CIS, COS>;
   __shared__ __attribute__((aligned(16))) u16 sE[COS * WG_PITCH];
   __shared__ __attribute__((aligned(16))) u16 sA[9 * CIS * WG_PITCH];
   const int lane = threadIdx.x & 63;
@@ -1459,16 +1389,15 @@ Features make_features(const tlb_cnn* net) {
   return F;
 }
 
-// index of a convolution variant: 0 moments input, 1 8-channel input, 2-4 32-channel input
-// with the output layer's, the ReLU-mask and the bias + ReLU epilogue
+// index of a convolution variant: 0 8-channel input with the bias + ReLU epilogue (the first
+// layer), 1 8-channel input with the ReLU mask, 2-4 32-channel input with the output layer's,
+// the ReLU-mask and the bias + ReLU epilogue
 int conv_variant(int in, int epi) {
-  if (in == IN_MOM) return 0;
-  if (in == IN_BF8) return 1;
+  if (in == IN_BF8) return epi == EPI_RELU ? 0 : 1;
   return epi == EPI_OUT ? 2 : epi == EPI_MASK ? 3 : 4;
 }
 
 const void* conv_fn(int in, int cob, int epi) {
-  if (in == IN_MOM) return reinterpret_cast<const void*>(&conv_kernel<IN_MOM, 2, EPI_RELU>);
   if (in == IN_BF8)
     return epi == EPI_RELU ? reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_RELU>)
                            : reinterpret_cast<const void*>(&conv_kernel<IN_BF8, 2, EPI_MASK>);
@@ -1479,16 +1408,13 @@ const void* conv_fn(int in, int cob, int epi) {
 }
 
 tlbi_launch conv_launch(const tlb_cnn* net, int in, int cob, int epi, const void* src,
-                        const int32_t* idx, const u16* w, const float* bias, const u16* mask,
-                        void* out, int n) {
+                        const u16* w, const float* bias, const u16* mask, void* out, int n) {
   ConvArgs a{};
   a.in = src;
-  a.idx = idx;
   a.w = reinterpret_cast<const bf16x8*>(w);
   a.bias = bias;
   a.mask = mask;
   a.out = out;
-  a.F = make_features(net);
   a.n = n;
   a.H = net->H;
   a.W = net->W;
@@ -1523,19 +1449,19 @@ tlbi_launch features_launch(const tlb_cnn* net, const float* moments, const int3
 void forward_seq(const tlb_cnn* net, const float* moments, const int32_t* idx, int n,
                  std::vector<tlbi_launch>& seq) {
   seq.push_back(features_launch(net, moments, idx, n));
-  seq.push_back(conv_launch(net, IN_BF8, 2, EPI_RELU, net->feat, nullptr, net->wf[0],
+  seq.push_back(conv_launch(net, IN_BF8, 2, EPI_RELU, net->feat, net->wf[0],
                             bias_of(net, 0), nullptr, net->act[0], n));
   for (int l = 1; l < 4; ++l)
-    seq.push_back(conv_launch(net, IN_BF32, 2, EPI_RELU, net->act[l - 1], nullptr, net->wf[l],
+    seq.push_back(conv_launch(net, IN_BF32, 2, EPI_RELU, net->act[l - 1], net->wf[l],
                               bias_of(net, l), nullptr, net->act[l], n));
-  seq.push_back(conv_launch(net, IN_BF32, 1, EPI_OUT, net->act[3], nullptr, net->wf[4],
+  seq.push_back(conv_launch(net, IN_BF32, 1, EPI_OUT, net->act[3], net->wf[4],
                             bias_of(net, 4), nullptr, net->z, n));
 }
 
 const void* wgrad_fn(int l) {
-  if (l == 0) return reinterpret_cast<const void*>(&wgrad_kernel<8, 32, false>);
-  if (l == 4) return reinterpret_cast<const void*>(&wgrad_kernel<32, 8, false>);
-  return reinterpret_cast<const void*>(&wgrad_kernel<32, 32, false>);
+  if (l == 0) return reinterpret_cast<const void*>(&wgrad_kernel<8, 32>);
+  if (l == 4) return reinterpret_cast<const void*>(&wgrad_kernel<32, 8>);
+  return reinterpret_cast<const void*>(&wgrad_kernel<32, 32>);
 }
 
 // loss, back-propagation and the gradient of every layer into net->grad
@@ -1563,10 +1489,8 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
   for (int l = NL - 1; l >= 0; --l) {
     WgradArgs wa{};
     wa.e = e;
-    wa.a = l == 0 ? static_cast<const void*>(net->feat) : static_cast<const void*>(net->act[l - 1]);
-    wa.idx = nullptr;
+    wa.a = l == 0 ? net->feat : net->act[l - 1];
     wa.partial = net->partial;
-    wa.F = make_features(net);
     wa.n = n;
     wa.H = net->H;
     wa.W = net->W;
@@ -1582,7 +1506,7 @@ void backward_seq(const tlb_cnn* net, const float* moments, const float* targets
     if (l > 0) {
       // error signals alternate between two buffers: layer 4 -> eA, 3 -> eB, 2 -> eA, ...
       u16* next = (l == 4 || e == net->eB) ? net->eA : net->eB;
-      seq.push_back(conv_launch(net, l == 4 ? IN_BF8 : IN_BF32, 2, EPI_MASK, e, nullptr,
+      seq.push_back(conv_launch(net, l == 4 ? IN_BF8 : IN_BF32, 2, EPI_MASK, e,
                                 net->wd[l], nullptr, net->act[l - 1], next, n));
       e = next;
     }
@@ -1883,9 +1807,9 @@ int32_t tlb_cnn_create(const tlb_cnn_desc* desc, void* hip_stream, tlb_cnn** out
   alloc((void**)&net->red, (size_t)net->red_blocks * 8 * 8);
   alloc((void**)&net->scalars, 8 * 8);
   alloc((void**)&net->Jrow, net->H * 4);
-  // partial sums of the corrections: one per row (tlb_apply_correction), per block of the
-  // output layer (forward), or per tile of the learned step's network
-  const size_t nproj = std::max<size_t>(std::max(net->H, CONV_MAX_BLOCKS), net_tiles(net->H, net->W));
+  // partial sums of the corrections: one per row (tlb_apply_correction) or per tile of the
+  // learned step's network
+  const size_t nproj = std::max<size_t>(net->H, net_tiles(net->H, net->W));
   alloc((void**)&net->proj, nproj * 3 * 8);
   if (e != hipSuccess) {
     free_net(net);
