@@ -635,7 +635,7 @@ __global__ __launch_bounds__(64 * GR_WAVES) void grad_reduce_kernel(GradArgs a) 
   const size_t stride = (size_t)a.cos_s * 9 * a.cis + a.cos_s;
   double s = 0.0;
   if (valid) {
-#pragma unroll 4
+#pragma unroll 16
     for (int b = quarter; b < a.blocks; b += GR_WAVES) s += (double)a.partial[b * stride + src];
   }
   part[quarter][lane] = s;
