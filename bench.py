@@ -554,6 +554,8 @@ def main():
                                    dt=p.dt / 2, nonfinite=d["nonfinite"])
         out["ensemble64_fp32"] = ensemble_leg()
         out["learned_coarse_fp32"] = learned_leg(t_fine)
+        # the network's training step (16 samples of 128 x 320, bf16 matrix cores), measured
+        out["cnn_training_bf16"] = training_timing(200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
