@@ -103,12 +103,13 @@ def test_gradient_matches_reference(torch_cuda, shape):
         o += nW + co
 
 
-@pytest.mark.parametrize("shape", [(8, 64, 136), (6, 48, 200)])
+@pytest.mark.parametrize("shape", [(8, 64, 136), (6, 48, 200), (32, 2, 832), (32, 1, 1600)])
 def test_forward_and_gradient_with_many_tiles_per_wavefront(torch_cuda, shape):
-    """More 64-node strips (1536, 1152) than weight-gradient workgroups and more 16-node tiles
-    (4608, 3744) than convolution wavefronts on this part, so that each walks several strips
-    or tiles, carrying across rows and samples, with ragged row ends (136 = 2 x 64 + 8,
-    200 = 3 x 64 + 8)."""
+    """More 64-node strips (1536, 1152, 832, 800) than weight-gradient workgroups and more
+    16-node tiles (4608, 3744, 3328, 3200) than convolution wavefronts on this part, so that
+    each walks several strips or tiles, carrying across rows and samples, with ragged row ends
+    (136 = 2 x 64 + 8, 200 = 3 x 64 + 8); with one or two rows the window of input rows and the
+    taps carried to the next row wrap onto themselves."""
     torch = torch_cuda
     n, H, W = shape
     params = params_with_biases(11)
