@@ -126,9 +126,9 @@ struct FeatArgs {
   int n, H, W;
 };
 
-// one workgroup per (row blockIdx.x, batch slot blockIdx.y)
+// one workgroup per row and batch slot: blockIdx.x = slot H + row
 __global__ __launch_bounds__(128) void features_kernel(FeatArgs a) {
-  const int y = blockIdx.x, slot = blockIdx.y;
+  const int y = blockIdx.x % a.H, slot = blockIdx.x / a.H;
   const int smp = a.idx ? a.idx[slot] : slot;
   // n H W < 2^28, checked when the network is created
   const float4* src = reinterpret_cast<const float4*>(a.m) + ((size_t)smp * a.H + y) * a.W;
@@ -1442,7 +1442,7 @@ tlbi_launch features_launch(const tlb_cnn* net, const float* moments, const int3
   fa.n = n;
   fa.H = net->H;
   fa.W = net->W;
-  return make_launch(reinterpret_cast<const void*>(&features_kernel), dim3(net->H, n), dim3(128),
+  return make_launch(reinterpret_cast<const void*>(&features_kernel), dim3(n * net->H), dim3(128),
                      fa);
 }
 

@@ -64,6 +64,22 @@ def test_forward_matches_reference(torch_cuda, shape):
     assert e2 <= 1e-3 and ei <= 1e-2
 
 
+def test_forward_more_samples_than_a_grid_dimension(torch_cuda):
+    """66000 samples of a 1 x 2 torus: more batch slots than a launch grid's second or third
+    dimension holds (65535), every tap wrapping onto the row's two nodes."""
+    torch = torch_cuda
+    n, H, W = 66000, 1, 2
+    params = params_with_biases(13)
+    m, _ = inputs.learn_samples(14, n, H, W)
+    net = make_net(torch, H, W, n, params)
+    out = net.forward(torch.tensor(m, device="cuda")).cpu().numpy().astype(np.float64)
+    _, z = C.forward(params.astype(np.float64), m.astype(np.float64), GEO["r"], GEO["R"], SHIFT, SCALE)
+    ref = z * np.array(OUT_SCALE)
+    e2, ei = rel_l2(out, ref), rel_linf(out, ref)
+    print(f"forward {n}x{H}x{W}: rel L2 {e2:.2e}, rel Linf {ei:.2e}", flush=True)
+    assert e2 <= 1e-3 and ei <= 1e-2
+
+
 def test_forward_full_coarse_grid(torch_cuda):
     """The 128 x 320 coarse grid the learned step runs on, one sample, all outputs."""
     torch = torch_cuda
